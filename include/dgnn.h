@@ -1,0 +1,238 @@
+/*
+ * dgnn.h -- C ABI of libdgnn.so: a nodal discontinuous Galerkin spectral
+ * element (DGSEM) solver of the 3D compressible Navier-Stokes equations on
+ * periodic hexahedral boxes, with a corrective-forcing neural network, for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of arXiv 2207.11571 ("Accelerating high order
+ * discontinuous Galerkin solvers using neural networks: 3D compressible
+ * Navier-Stokes equations"): a low-order DG operator p_LO plus a learned
+ * forcing s (Eq. (4)), the forcing trained on s = G p_HO(q_HO) - p_LO(G q_HO)
+ * (Eq. (5)), advanced with a three-stage third-order Runge-Kutta scheme.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Return value: DG_OK (0) or a negative DG_E* code; dg_last_error() gives the
+ *   text of the last failure on the calling thread.  No exception crosses the
+ *   ABI.  Kernel execution errors surface at the next call or synchronisation.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Launch calls enqueue on it and return without synchronising unless stated.
+ * Ownership: every device buffer (state, register, residual, workspace,
+ *   weights, datasets, serving arena) is allocated by the caller and passed as
+ *   a raw device pointer; the library never allocates per-solve device data.
+ *   Opaque handles (dg_mesh, nn_model, solve_server) are host objects owned by
+ *   the library and released with the matching *_free call.
+ * Alignment: device buffers must be 256-byte aligned and must not alias each
+ *   other unless stated.
+ * State layout: q is double[5][E][n_p], E = N^3 elements, n_p = (P+1)^3 nodes,
+ *   variables (rho, rho u, rho v, rho w, rho e); element e = ex + N (ey + N ez);
+ *   node n = i + (P+1)(j + (P+1) k) with i along x; node (i, j, k) of element
+ *   (ex, ey, ez) sits at x = ex h + (xi_i + 1) h / 2 (xi = Gauss-Legendre
+ *   points), h = L / N, and likewise in y and z.
+ */
+#ifndef DGNN_H
+#define DGNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DG_OK = 0,
+    DG_EINVAL = -1,      /* null/aliased pointer, unsupported P or N, bad size     */
+    DG_ENOSPC = -2,      /* workspace or arena too small                           */
+    DG_EHIP = -3,        /* HIP runtime or launch error                            */
+    DG_EAGAIN = -4,      /* solve_poll: not finished yet                           */
+    DG_ENOENT = -5,      /* unknown request id                                     */
+    DG_ENONFINITE = -6   /* NaN or Inf detected in a solve                         */
+};
+
+#define DG_MIN_ORDER 1
+#define DG_MAX_ORDER 8
+
+/* Copies the calling thread's last error text into buf (NUL-terminated). */
+int dg_last_error(char* buf, size_t len);
+
+/* ------------------------------------------------------------------ mesh */
+
+/* Physical and discretisation parameters (Sec. 3.1 and App. A).
+ * Nondimensionalisation: rho0 = V0 = 1, unit length, box side L (2 pi for the
+ * Taylor-Green vortex), mu = 1/Re, T = p/rho, kappa = mu gamma/((gamma-1) Pr).
+ * Cs > 0 switches on the Smagorinsky closure mu_t = rho (Cs h/(P+1))^2 |S|,
+ * with turbulent Prandtl number Pr_t.  viscous = 0 gives the Euler equations.
+ * p_ref is subtracted from the momentum fluxes (it changes the residual only
+ * by rounding); pass p0 = 1/(gamma Mach^2). */
+typedef struct dg_params {
+    int32_t N;          /* elements per direction, 1..1024                     */
+    int32_t P;          /* polynomial order, DG_MIN_ORDER..DG_MAX_ORDER          */
+    int32_t viscous;    /* 1 Navier-Stokes (BR1), 0 Euler                       */
+    int32_t reserved;
+    double L;           /* box side                                              */
+    double Re, Mach, gamma, Pr, Cs, Pr_t, p_ref;
+} dg_params;
+
+typedef struct dg_mesh dg_mesh;
+
+/* Builds the Gauss-Legendre basis tables on the host, uploads them to the
+ * current device and returns a mesh handle.  DG_EINVAL for an unsupported
+ * P or N or a non-positive physical parameter. */
+int dg_init_mesh(const dg_params* prm, dg_mesh** out);
+
+/* Node count E n_p and the workspace bytes every dg_* call on this mesh
+ * needs (face traces, interface fluxes, forcing and reduction buffers). */
+int dg_mesh_query(const dg_mesh* m, int64_t* n_nodes, size_t* workspace_bytes);
+
+void dg_free_mesh(dg_mesh* m);
+
+/* Taylor-Green vortex initial condition, Eq. (11), written into q. */
+int dg_init_tgv(const dg_mesh* m, double* q, void* stream);
+
+/* dqdt = p(q): the weak-form DGSEM operator of Eq. (1)/(3) -- volume flux
+ * divergence, Roe interface flux, BR1 gradients and viscous fluxes, optional
+ * Smagorinsky closure.  No forcing.  q and dqdt must not alias. */
+int dg_residual(const dg_mesh* m, const double* q, double* dqdt,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* n_steps steps of the low-storage three-stage third-order Runge-Kutta
+ * scheme (Sec. 3.1) of dq/dt = p(q) + s(q) (Eq. (4)), in place on q; k is
+ * the Runge-Kutta register (same layout, contents on entry are ignored).
+ * forcing == NULL advances the uncorrected low-order system (Eq. (3)); with a
+ * model, s(q) is evaluated at every stage on the stage state. */
+typedef struct nn_model nn_model;
+int dg_rk_step(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps,
+               const nn_model* forcing, void* ws, size_t ws_bytes, void* stream);
+
+/* Diagnostics, written to out_dev (device, double[8]):
+ * [0] kinetic energy (volume mean of rho |v|^2 / 2), [1] max over nodes of
+ * |v| + c, [2] min density, [3..7] integrals of the five conserved variables.
+ * The reduction order is fixed: results are bitwise reproducible. */
+int dg_diagnostics(const dg_mesh* m, const double* q, double* out_dev,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Time step of Eq. (7) with the (P+1)^2 order scaling, from the state q:
+ * min(CFL h/((P+1)^2 max(|v|+c)), CFL h^2/((P+1)^4 max(nu, gamma nu/Pr))),
+ * nu = mu/min(rho).  Synchronises `stream`; *dt_host receives the value. */
+int dg_stable_dt(const dg_mesh* m, const double* q, double cfl, double* dt_host,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Infinity-norm error of Eq. (9) for rho u, rho v, rho w between q and q_ref
+ * (same mesh): out_dev (device, double[3]). */
+int dg_error_inf(const dg_mesh* m, const double* q, const double* q_ref, double* out_dev,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* The filter G of Sec. 2: nodal -> Legendre modal -> truncate -> nodal, per
+ * element, from mesh src (order P_src) to mesh dst (same N, P_dst <= P_src).
+ * Works on any 5-variable field (states and residuals alike). */
+int dg_project(const dg_mesh* src, const dg_mesh* dst, const double* f_src, double* f_dst, void* stream);
+
+/* Training pairs of Eq. (5) for one high-order snapshot q_hi:
+ * x = G q_hi and y = G p_hi(q_hi) - p_lo(G q_hi), written as float rows
+ * x_out[E][5 n_p_lo], y_out[E][5 n_p_lo] (row = element, variable-major).
+ * ws must hold dg_forcing_target_ws() bytes. */
+size_t dg_forcing_target_ws(const dg_mesh* hi, const dg_mesh* lo);
+int dg_forcing_target(const dg_mesh* hi, const dg_mesh* lo, const double* q_hi,
+                      float* x_out, float* y_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------- forcing network */
+
+/* The fully connected forcing network of Sec. 2.2, one network shared by all
+ * elements: dims[0] = 5 n_p inputs (the element's state, variable-major),
+ * hidden layers of dims[1..n_layers-1] units, dims[n_layers] = 5 n_p outputs.
+ * Hidden activation: 0 = tanh, 1 = relu; the output layer is linear.
+ * Parameters (caller-owned, device, float32) are packed layer by layer as
+ * W_l[out][in] row-major followed by b_l[out].  The library keeps bfloat16
+ * copies of the weights (w_bf16, caller-owned, nn_query's n_bf16 elements)
+ * for the matrix cores; biases stay float32.
+ * norm (host, copied): mu_in[5], sigma_in[5], mu_out[5], sigma_out[5]:
+ *   xhat = (x - mu_in[v]) / sigma_in[v],  s = mask[v] (sigma_out[v] yhat + mu_out[v]).
+ * grad, adam_m, adam_v (device float32, n_params each) may be NULL for an
+ * inference-only model; nn_init zeroes adam_m and adam_v. */
+int nn_query(const int32_t* dims, int32_t n_layers, int64_t* n_params, int64_t* n_bf16);
+int nn_init(const int32_t* dims, int32_t n_layers, int32_t activation,
+            float* params, uint16_t* w_bf16, float* grad, float* adam_m, float* adam_v,
+            const double* norm, const uint8_t* mask, void* stream, nn_model** out);
+/* Re-derives the bfloat16 copies after the caller rewrote params. */
+int nn_refresh(nn_model* model, void* stream);
+/* Replaces the normalisation (host array of 20 doubles) and the mask. */
+int nn_set_norm(nn_model* model, const double* norm, const uint8_t* mask);
+void nn_free(nn_model* model);
+
+/* dqdt += s(q) for every element of mesh m (bfloat16 matrix-core products,
+ * float32 accumulation, float32 bias and activation, bfloat16 activations
+ * between layers, float32 output, float64 forcing). */
+int nn_forcing(const nn_model* model, const dg_mesh* m, const double* q, double* dqdt,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of one nn_train_step with `batch` rows. */
+size_t nn_train_ws(const nn_model* model, int32_t batch);
+
+/* One Adam step (Kingma-Ba, bias-corrected, beta1 0.9, beta2 0.999, eps 1e-7)
+ * of the MSE loss mean((yhat - (y - mu_out)/sigma_out)^2) on the batch
+ * x[batch][n_in], y[batch][n_out] (float32 rows in physical units, device).
+ * Forward and backward run on bfloat16 matrix cores with float32
+ * accumulation; the float32 master weights, grad, adam_m, adam_v are
+ * updated in place and the bfloat16 copies refreshed.  loss_dev (device
+ * float, may be NULL) receives the batch loss before the update. */
+int nn_train_step(nn_model* model, const float* x, const float* y, int32_t batch, float lr,
+                  float* loss_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------- serving */
+
+/* A continuous-batching server of Taylor-Green solves (one host thread and
+ * one HIP stream of its own).  Solves are admitted by device footprint into
+ * the caller's arena; the Runge-Kutta stages of all running solves of the
+ * same order run in shared launches, so requests that arrive while others run
+ * join them at the next step.  Each solve computes exactly what it would
+ * compute alone (no cross-solve reductions). */
+typedef struct solve_server solve_server;
+
+typedef struct solve_request {
+    double Re, t_end, Mach, Cs;     /* Mach <= 0 means 0.1                         */
+    int32_t P, N, use_nn;           /* use_nn requires model                       */
+    int32_t ke_every;               /* record KE every ke_every steps (>= 1)       */
+    const nn_model* model;
+    double* ke_host;                /* host, ke_capacity doubles (t, KE) pairs; may be NULL */
+    int32_t ke_capacity;            /* number of (t, KE) pairs ke_host holds       */
+    int32_t reserved;
+    double* q_out_host;             /* host, final state 5 E n_p doubles; may be NULL */
+} solve_request;
+
+enum { SOLVE_QUEUED = 0, SOLVE_RUNNING = 1, SOLVE_DONE = 2, SOLVE_FAILED = 3 };
+
+typedef struct solve_status {
+    int32_t state;                  /* SOLVE_*                                     */
+    int32_t error;                  /* DG_* code when failed                       */
+    int64_t steps, n_steps;         /* executed / total Runge-Kutta steps          */
+    int32_t ke_count;               /* (t, KE) pairs written                       */
+    int32_t reserved;
+    double t, dt;                   /* physical time reached, step size            */
+    double latency_s;               /* completion - submission (done only)         */
+    double queue_s;                 /* admission - submission                      */
+    int64_t dof_updates;            /* E n_p x executed stages                     */
+} solve_status;
+
+/* Bytes a solve of order P on N^3 elements occupies in the arena. */
+size_t solve_footprint(int32_t P, int32_t N, int32_t use_nn);
+int solve_server_create(void* arena, size_t arena_bytes, int32_t max_slots, solve_server** out);
+/* Thread-safe and non-blocking.  DG_ENOSPC at once when the request can never
+ * fit the arena; otherwise queued until a slot and arena space are free. */
+int solve_submit(solve_server* srv, const solve_request* req, uint64_t* id);
+/* Non-blocking: DG_OK with st filled when done or failed, DG_EAGAIN with st
+ * filled while queued or running, DG_ENOENT for an unknown id. */
+int solve_poll(solve_server* srv, uint64_t id, solve_status* st);
+/* Blocks until no request is queued or running. */
+int solve_server_drain(solve_server* srv);
+/* Host-side test hook: on the next step boundary of request id, writes a NaN
+ * into its state (exercises the non-finite detection of one solve). */
+int solve_inject_nan(solve_server* srv, uint64_t id);
+/* Totals: device-busy seconds (sum of step-batch wall times), launches. */
+int solve_server_stats(solve_server* srv, double* busy_s, int64_t* batches);
+void solve_server_free(solve_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

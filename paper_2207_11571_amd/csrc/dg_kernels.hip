@@ -1,0 +1,853 @@
+// FP64 DGSEM kernels for gfx950: face traces, BR1 gradient pass, residual and
+// Runge-Kutta stage update, Taylor-Green initial condition, diagnostics,
+// filter G and training-pair packing.
+//
+// Discretisation (Sec. 2.6, Sec. 3.1, App. A): weak-form nodal DGSEM on
+// Gauss-Legendre points, Roe interface flux, BR1 gradients of (u, v, w, T)
+// and viscous fluxes, optional Smagorinsky closure, on uniform periodic
+// hexahedra.  One workgroup owns one element; thread t owns node t
+// (n = i + PP (j + PP k)); the element's state is staged in LDS so that the
+// (P+1)-long line contractions of the sum-factorised operators read LDS.
+//
+// Per Runge-Kutta stage two kernels run (BR1 needs neighbours' gradients,
+// which need their neighbours' traces):
+//   k_grad  : q, neighbour q traces -> BR1 gradient -> one-sided viscous
+//             normal flux on the element's six faces (fv);
+//   k_resid : q, neighbour q traces, fv of both sides -> Roe minus averaged
+//             viscous interface flux, volume flux divergence, forcing ->
+//             residual, or the low-storage stage update of q and k plus the
+//             face traces of the new q for the next stage.
+#include "dgnn_internal.hpp"
+
+namespace dgnn {
+
+__constant__ BasisTab c_basis[DG_MAX_ORDER];
+
+template <int PP>
+struct Shape {
+    static constexpr int NP = PP * PP * PP;
+    static constexpr int NF = PP * PP;
+    static constexpr int NT = ((NP + 63) / 64) * 64;
+    static constexpr int NFT = 6 * NF;                  // face-node tasks
+    static constexpr int TPT = (NFT + NT - 1) / NT;     // tasks per thread
+};
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+__device__ __forceinline__ int find_solve(const DescList& dl, int b) {
+    int s = 0;
+    for (int i = 1; i < dl.n; ++i)
+        if (dl.blk[i] <= b) s = i;
+    return s;
+}
+
+__device__ __forceinline__ int neighbour(int e, int N, int f) {
+    int ex = e % N, ey = (e / N) % N, ez = e / (N * N);
+    const int d = f >> 1;
+    const int step = (f & 1) ? 1 : N - 1;
+    if (d == 0) ex = (ex + step) % N;
+    else if (d == 1) ey = (ey + step) % N;
+    else ez = (ez + step) % N;
+    return ex + N * (ey + N * ez);
+}
+
+// node of the line through face-node (a, b) of a face normal to d, at position m
+template <int PP>
+__device__ __forceinline__ int line_node(int d, int a, int b, int m) {
+    return d == 0 ? m + PP * (a + PP * b) : (d == 1 ? a + PP * (m + PP * b) : a + PP * (b + PP * m));
+}
+
+// --------------------------------------------------------------- physics
+
+// w = (u, v, w, T) with T = p / rho
+__device__ __forceinline__ void gradient_vars(const double q[5], double gm1, double w[4]) {
+    const double ir = 1.0 / q[0];
+    w[0] = q[1] * ir;
+    w[1] = q[2] * ir;
+    w[2] = q[3] * ir;
+    const double p = gm1 * (q[4] - 0.5 * (q[1] * w[0] + q[2] * w[1] + q[3] * w[2]));
+    w[3] = p * ir;
+}
+
+__device__ __forceinline__ double pressure(const double q[5], double gm1) {
+    const double ir = 1.0 / q[0];
+    return gm1 * (q[4] - 0.5 * ir * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
+}
+
+// inviscid flux along D (App. A), p_ref removed from the momentum rows
+template <int D>
+__device__ __forceinline__ void flux_inviscid(const double q[5], double gm1, double p_ref, double F[5]) {
+    const double ir = 1.0 / q[0];
+    const double vd = q[1 + D] * ir;
+    const double p = pressure(q, gm1);
+    F[0] = q[1 + D];
+    F[1] = q[1] * vd;
+    F[2] = q[2] * vd;
+    F[3] = q[3] * vd;
+    F[1 + D] += p - p_ref;
+    F[4] = (q[4] + p) * vd;
+}
+
+// Roe flux along +D, qL on the lower side (Roe 1981), no entropy fix
+template <int D>
+__device__ void flux_roe(const double qL[5], const double qR[5], const Phys& ph, double F[5]) {
+    const double gm1 = ph.gm1;
+    const double rL = qL[0], rR = qR[0];
+    const double iL = 1.0 / rL, iR = 1.0 / rR;
+    double vL[3], vR[3];
+    for (int a = 0; a < 3; ++a) { vL[a] = qL[1 + a] * iL; vR[a] = qR[1 + a] * iR; }
+    const double pL = gm1 * (qL[4] - 0.5 * rL * (vL[0] * vL[0] + vL[1] * vL[1] + vL[2] * vL[2]));
+    const double pR = gm1 * (qR[4] - 0.5 * rR * (vR[0] * vR[0] + vR[1] * vR[1] + vR[2] * vR[2]));
+    const double HL = (qL[4] + pL) * iL, HR = (qR[4] + pR) * iR;
+    const double sL = sqrt(rL), sR = sqrt(rR);
+    const double rt = sL * sR;
+    const double isum = 1.0 / (sL + sR);
+    double vt[3];
+    for (int a = 0; a < 3; ++a) vt[a] = (sL * vL[a] + sR * vR[a]) * isum;
+    const double Ht = (sL * HL + sR * HR) * isum;
+    const double v2 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
+    const double ct = sqrt(gm1 * (Ht - 0.5 * v2));
+    const double vn = vt[D];
+    const double ic2 = 1.0 / (ct * ct);
+    const double dr = rR - rL, dp = pR - pL;
+    double dv[3];
+    for (int a = 0; a < 3; ++a) dv[a] = vR[a] - vL[a];
+    // wave strengths times |eigenvalue|
+    const double wm = fabs(vn - ct) * (dp - rt * ct * dv[D]) * 0.5 * ic2;
+    const double wp = fabs(vn + ct) * (dp + rt * ct * dv[D]) * 0.5 * ic2;
+    const double l0 = fabs(vn);
+    const double we = l0 * (dr - dp * ic2);
+    double diss[5];
+    diss[0] = wm + we + wp;
+    double de = wm * (Ht - ct * vn) + we * 0.5 * v2 + wp * (Ht + ct * vn);
+    for (int a = 0; a < 3; ++a) {
+        double m = (wm + we + wp) * vt[a];
+        if (a == D) {
+            m += (wp - wm) * ct;
+        } else {
+            const double ws = l0 * rt * dv[a];   // shear wave
+            m += ws;
+            de += ws * vt[a];
+        }
+        diss[1 + a] = m;
+    }
+    diss[4] = de;
+    double FL[5], FR[5];
+    // central part from the primitive values already at hand
+    {
+        const double vdL = vL[D], vdR = vR[D];
+        FL[0] = qL[1 + D];  FR[0] = qR[1 + D];
+        FL[1] = qL[1] * vdL; FR[1] = qR[1] * vdR;
+        FL[2] = qL[2] * vdL; FR[2] = qR[2] * vdR;
+        FL[3] = qL[3] * vdL; FR[3] = qR[3] * vdR;
+        FL[1 + D] += pL - ph.p_ref;
+        FR[1 + D] += pR - ph.p_ref;
+        FL[4] = (qL[4] + pL) * vdL;
+        FR[4] = (qR[4] + pR) * vdR;
+    }
+    for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * diss[v];
+}
+
+// One-sided viscous flux along D (App. A): momentum rows tau_{aD} and the
+// energy row sum_a v_a tau_{aD} + kappa dT/dx_D.  g[j][c] = d_j w_c.
+template <int D>
+__device__ __forceinline__ void flux_viscous(double rho, const double v[3], const double g[3][4],
+                                             const Phys& ph, double Fv[4]) {
+    double mu = ph.mu, kappa = ph.kappa;
+    if (ph.les) {
+        double SS = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double Sab = 0.5 * (g[a][b] + g[b][a]);
+                SS += Sab * Sab;
+            }
+        const double mut = rho * ph.les_c * sqrt(2.0 * SS);
+        mu += mut;
+        kappa += mut * ph.kt;
+    }
+    const double div = g[0][0] + g[1][1] + g[2][2];
+    double e = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double tau = mu * (g[a][D] + g[D][a]);
+        if (a == D) tau -= (2.0 / 3.0) * mu * div;
+        Fv[a] = tau;
+        e += v[a] * tau;
+    }
+    Fv[3] = e + kappa * g[D][3];
+}
+
+template <int D>
+__device__ __forceinline__ void flux_net(const double q[5], const double g[3][4], const Phys& ph, double G[5]) {
+    flux_inviscid<D>(q, ph.gm1, ph.p_ref, G);
+    if (ph.viscous) {
+        const double ir = 1.0 / q[0];
+        const double v[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+        double Fv[4];
+        flux_viscous<D>(q[0], v, g, ph, Fv);
+        G[1] -= Fv[0];
+        G[2] -= Fv[1];
+        G[3] -= Fv[2];
+        G[4] -= Fv[3];
+    }
+}
+
+__device__ __forceinline__ void flux_viscous_dir(int d, double rho, const double v[3], const double g[3][4],
+                                                 const Phys& ph, double Fv[4]) {
+    if (d == 0) flux_viscous<0>(rho, v, g, ph, Fv);
+    else if (d == 1) flux_viscous<1>(rho, v, g, ph, Fv);
+    else flux_viscous<2>(rho, v, g, ph, Fv);
+}
+
+__device__ __forceinline__ void flux_roe_dir(int d, const double qL[5], const double qR[5], const Phys& ph,
+                                             double F[5]) {
+    if (d == 0) flux_roe<0>(qL, qR, ph, F);
+    else if (d == 1) flux_roe<1>(qL, qR, ph, F);
+    else flux_roe<2>(qL, qR, ph, F);
+}
+
+// ----------------------------------------------------- element-local pieces
+
+// trace of the nodal field sh[v*NP + n] (v < nv) on face f at face node fn
+template <int PP, int NV>
+__device__ __forceinline__ void face_interp(const double* __restrict__ sh, const BasisTab& B, int f, int fn,
+                                            double out[NV]) {
+    constexpr int NP = PP * PP * PP;
+    const int d = f >> 1;
+    const int a = fn % PP, b = fn / PP;
+    const double* bv = (f & 1) ? B.bp : B.bm;
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+#pragma unroll
+    for (int m = 0; m < PP; ++m) {
+        const int n = line_node<PP>(d, a, b, m);
+        const double c = bv[m];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] += c * sh[v * NP + n];
+    }
+}
+
+// weak-form derivative along D at node t of the nodal field sh[c*NP + .] with
+// interface values fhat[(f*NC + c)*NF + fn]:
+//   s [ b+_i/w_i Fhat(+) - b-_i/w_i Fhat(-) - sum_m Dhat[i][m] F_m ]
+template <int PP, int D, int NC>
+__device__ __forceinline__ void weak_deriv(const double* __restrict__ sh, const double* __restrict__ fhat,
+                                           const BasisTab& B, int t, double s, double out[NC]) {
+    constexpr int NP = PP * PP * PP;
+    constexpr int NF = PP * PP;
+    constexpr int stride = D == 0 ? 1 : (D == 1 ? PP : PP * PP);
+    const int i = t % PP, j = (t / PP) % PP, k = t / (PP * PP);
+    const int id = D == 0 ? i : (D == 1 ? j : k);
+    const int fn = D == 0 ? j + PP * k : (D == 1 ? i + PP * k : i + PP * j);
+    const int base = t - id * stride;
+    double acc[NC];
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int m = 0; m < PP; ++m) {
+        const double dm = B.Dhat[id * PP + m];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += dm * sh[c * NP + base + m * stride];
+    }
+    const double lp = B.bpw[id], lm = B.bmw[id];
+    const int fp = 2 * D + 1, fm = 2 * D;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        out[c] = s * (lp * fhat[(fp * NC + c) * NF + fn] - lm * fhat[(fm * NC + c) * NF + fn] - acc[c]);
+}
+
+// q of this thread's node into LDS, then the six face traces to global
+template <int PP>
+__device__ __forceinline__ void write_traces(double* sh, const BasisTab& B, int t, int e, double* __restrict__ out) {
+    using S = Shape<PP>;
+#pragma unroll
+    for (int r = 0; r < S::TPT; ++r) {
+        const int tau = t + r * S::NT;
+        if (tau < S::NFT) {
+            const int f = tau / S::NF, fn = tau - f * S::NF;
+            double qi[5];
+            face_interp<PP, 5>(sh, B, f, fn, qi);
+            double* o = out + (size_t)(e * 6 + f) * 5 * S::NF + fn;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) o[v * S::NF] = qi[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <int PP>
+__global__ void __launch_bounds__(Shape<PP>::NT) k_traces(DescList dl) {
+    using S = Shape<PP>;
+    __shared__ double sh[5 * S::NP];
+    const int b = blockIdx.x;
+    const int si = find_solve(dl, b);
+    const SolveDesc& D = *dl.d[si];
+    const int e = b - dl.blk[si];
+    const int E = D.E;
+    const int t = threadIdx.x;
+    const BasisTab& B = c_basis[PP - 2];
+    if (t < S::NP)
+        for (int v = 0; v < 5; ++v) sh[v * S::NP + t] = D.q[((size_t)v * E + e) * S::NP + t];
+    __syncthreads();
+    write_traces<PP>(sh, B, t, e, D.qtr_out);
+}
+
+// BR1 pass: one-sided viscous normal fluxes on the six faces of each element.
+template <int PP>
+__global__ void __launch_bounds__(Shape<PP>::NT) k_grad(DescList dl) {
+    using S = Shape<PP>;
+    constexpr int NP = S::NP, NF = S::NF;
+    constexpr int LDS = cmax(12 * NP, 5 * NP + 24 * NF);
+    __shared__ double sh[LDS];
+    double* what = sh + 5 * NP;                  // [6][4][NF] common BR1 values
+    const int b = blockIdx.x;
+    const int si = find_solve(dl, b);
+    const SolveDesc& D = *dl.d[si];
+    const Phys ph = D.ph;
+    const int e = b - dl.blk[si];
+    const int E = D.E;
+    const int t = threadIdx.x;
+    const BasisTab& B = c_basis[PP - 2];
+
+    double qn[5];
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qn[v] = D.q[((size_t)v * E + e) * NP + t];
+            sh[v * NP + t] = qn[v];
+        }
+    }
+    __syncthreads();
+
+    double fq[S::TPT][4];   // own traced (rho, u, v, w) per face task
+#pragma unroll
+    for (int r = 0; r < S::TPT; ++r) {
+        const int tau = t + r * S::NT;
+        if (tau < S::NFT) {
+            const int f = tau / NF, fn = tau - f * NF;
+            double qi[5], qo[5];
+            face_interp<PP, 5>(sh, B, f, fn, qi);
+            const int nb = neighbour(e, D.N, f);
+            const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qo[v] = tr[v * NF];
+            double wi[4], wo[4];
+            gradient_vars(qi, ph.gm1, wi);
+            gradient_vars(qo, ph.gm1, wo);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) what[(f * 4 + c) * NF + fn] = 0.5 * (wi[c] + wo[c]);
+            fq[r][0] = qi[0];
+            fq[r][1] = wi[0];
+            fq[r][2] = wi[1];
+            fq[r][3] = wi[2];
+        }
+    }
+    __syncthreads();
+    if (t < NP) {
+        double w[4];
+        gradient_vars(qn, ph.gm1, w);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sh[c * NP + t] = w[c];
+    }
+    __syncthreads();
+    double g[3][4];
+    if (t < NP) {
+        weak_deriv<PP, 0, 4>(sh, what, B, t, ph.s, g[0]);
+        weak_deriv<PP, 1, 4>(sh, what, B, t, ph.s, g[1]);
+        weak_deriv<PP, 2, 4>(sh, what, B, t, ph.s, g[2]);
+    }
+    __syncthreads();
+    if (t < NP) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sh[(d * 4 + c) * NP + t] = g[d][c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < S::TPT; ++r) {
+        const int tau = t + r * S::NT;
+        if (tau < S::NFT) {
+            const int f = tau / NF, fn = tau - f * NF;
+            double gi[12];
+            face_interp<PP, 12>(sh, B, f, fn, gi);
+            double gf[3][4];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) gf[d][c] = gi[d * 4 + c];
+            const double v[3] = {fq[r][1], fq[r][2], fq[r][3]};
+            double Fv[4];
+            flux_viscous_dir(f >> 1, fq[r][0], v, gf, ph, Fv);
+            double* o = D.fv + (size_t)(e * 6 + f) * 4 * NF + fn;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o[c * NF] = Fv[c];
+        }
+    }
+}
+
+// Residual (update == 0: out = p(q) + forcing) or Runge-Kutta stage
+// (update == 1: k <- A k + dt R, q <- q + B k, traces of the new q).
+template <int PP, int UPDATE>
+__global__ void __launch_bounds__(Shape<PP>::NT)
+k_resid(DescList dl, double rkA, double rkB, int first_stage) {
+    using S = Shape<PP>;
+    constexpr int NP = S::NP, NF = S::NF;
+    __shared__ double sh[5 * NP + 54 * NF];
+    double* fhat = sh + 5 * NP;          // [6][5][NF] net interface flux
+    double* what = fhat + 30 * NF;       // [6][4][NF] common BR1 values
+    const int b = blockIdx.x;
+    const int si = find_solve(dl, b);
+    const SolveDesc& D = *dl.d[si];
+    const Phys ph = D.ph;
+    const int e = b - dl.blk[si];
+    const int E = D.E;
+    const int t = threadIdx.x;
+    const BasisTab& B = c_basis[PP - 2];
+    const size_t node = (size_t)e * NP + t;
+    const size_t vstride = (size_t)E * NP;
+
+    double qn[5];
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qn[v] = D.q[v * vstride + node];
+            sh[v * NP + t] = qn[v];
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int r = 0; r < S::TPT; ++r) {
+        const int tau = t + r * S::NT;
+        if (tau < S::NFT) {
+            const int f = tau / NF, fn = tau - f * NF;
+            const int d = f >> 1;
+            double qi[5], qo[5];
+            face_interp<PP, 5>(sh, B, f, fn, qi);
+            const int nb = neighbour(e, D.N, f);
+            const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qo[v] = tr[v * NF];
+            double F[5];
+            if (f & 1) flux_roe_dir(d, qi, qo, ph, F);
+            else flux_roe_dir(d, qo, qi, ph, F);
+            if (ph.viscous) {
+                const double* fi = D.fv + (size_t)(e * 6 + f) * 4 * NF + fn;
+                const double* fo = D.fv + (size_t)(nb * 6 + (f ^ 1)) * 4 * NF + fn;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) F[1 + c] -= 0.5 * (fi[c * NF] + fo[c * NF]);
+                double wi[4], wo[4];
+                gradient_vars(qi, ph.gm1, wi);
+                gradient_vars(qo, ph.gm1, wo);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) what[(f * 4 + c) * NF + fn] = 0.5 * (wi[c] + wo[c]);
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) fhat[(f * 5 + v) * NF + fn] = F[v];
+        }
+    }
+    __syncthreads();
+
+    double g[3][4];
+    if (ph.viscous) {
+        if (t < NP) {
+            double w[4];
+            gradient_vars(qn, ph.gm1, w);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sh[c * NP + t] = w[c];
+        }
+        __syncthreads();
+        if (t < NP) {
+            weak_deriv<PP, 0, 4>(sh, what, B, t, ph.s, g[0]);
+            weak_deriv<PP, 1, 4>(sh, what, B, t, ph.s, g[1]);
+            weak_deriv<PP, 2, 4>(sh, what, B, t, ph.s, g[2]);
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) g[d][c] = 0.0;
+    }
+
+    double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        __syncthreads();
+        if (t < NP) {
+            double G[5];
+            if (d == 0) flux_net<0>(qn, g, ph, G);
+            else if (d == 1) flux_net<1>(qn, g, ph, G);
+            else flux_net<2>(qn, g, ph, G);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sh[v * NP + t] = G[v];
+        }
+        __syncthreads();
+        if (t < NP) {
+            double dv[5];
+            if (d == 0) weak_deriv<PP, 0, 5>(sh, fhat, B, t, ph.s, dv);
+            else if (d == 1) weak_deriv<PP, 1, 5>(sh, fhat, B, t, ph.s, dv);
+            else weak_deriv<PP, 2, 5>(sh, fhat, B, t, ph.s, dv);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) R[v] -= dv[v];
+        }
+    }
+
+    if (t < NP && D.forcing) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) R[v] += D.forcing[v * vstride + node];
+    }
+
+    if (!UPDATE) {
+        if (t < NP) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) D.out[v * vstride + node] = R[v];
+        }
+        return;
+    }
+
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double kk = first_stage ? D.dt * R[v] : rkA * D.k[v * vstride + node] + D.dt * R[v];
+            qn[v] += rkB * kk;
+            D.k[v * vstride + node] = kk;
+            D.q[v * vstride + node] = qn[v];
+        }
+    }
+    __syncthreads();
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sh[v * NP + t] = qn[v];
+    }
+    __syncthreads();
+    write_traces<PP>(sh, B, t, e, D.qtr_out);
+}
+
+// Taylor-Green vortex initial condition, Eq. (11), on [0, L]^3.
+template <int PP>
+__global__ void __launch_bounds__(Shape<PP>::NT) k_tgv(Phys ph, int N, double* __restrict__ q) {
+    using S = Shape<PP>;
+    const int e = blockIdx.x;
+    const int t = threadIdx.x;
+    if (t >= S::NP) return;
+    const BasisTab& B = c_basis[PP - 2];
+    const int i = t % PP, j = (t / PP) % PP, k = t / (PP * PP);
+    const int ex = e % N, ey = (e / N) % N, ez = e / (N * N);
+    const double h = ph.h;
+    const double x = ex * h + (B.nodes[i] + 1.0) * h * 0.5;
+    const double y = ey * h + (B.nodes[j] + 1.0) * h * 0.5;
+    const double z = ez * h + (B.nodes[k] + 1.0) * h * 0.5;
+    const double u = sin(x) * cos(y) * cos(z);
+    const double v = -cos(x) * sin(y) * cos(z);
+    const double p = ph.p0 + (cos(2.0 * x) + cos(2.0 * y)) * (cos(2.0 * z) + 2.0) / 16.0;
+    const size_t vs = (size_t)N * N * N * S::NP;
+    const size_t n = (size_t)e * S::NP + t;
+    q[n] = 1.0;
+    q[vs + n] = u;
+    q[2 * vs + n] = v;
+    q[3 * vs + n] = 0.0;
+    q[4 * vs + n] = p / ph.gm1 + 0.5 * (u * u + v * v);
+}
+
+// Per-element partial diagnostics: KE integrand sum, max(|v| + c), min rho,
+// integrals of the five conserved variables (quadrature-weighted).  Fixed
+// reduction order, so the result is bitwise reproducible.
+template <int PP>
+__global__ void __launch_bounds__(256) k_diag_partial(Phys ph, int E, const double* __restrict__ q,
+                                                     double* __restrict__ part) {
+    constexpr int NP = PP * PP * PP;
+    __shared__ double red[8][256];
+    const int e = blockIdx.x;
+    const int t = threadIdx.x;
+    const BasisTab& B = c_basis[PP - 2];
+    double val[8] = {0.0, 0.0, 1e300, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const size_t vs = (size_t)E * NP;
+    for (int n = t; n < NP; n += 256) {
+        const int i = n % PP, j = (n / PP) % PP, k = n / (PP * PP);
+        const double wq = B.w[i] * B.w[j] * B.w[k];
+        double qq[5];
+        for (int v = 0; v < 5; ++v) qq[v] = q[v * vs + (size_t)e * NP + n];
+        const double ir = 1.0 / qq[0];
+        const double m2 = qq[1] * qq[1] + qq[2] * qq[2] + qq[3] * qq[3];
+        val[0] += wq * 0.5 * m2 * ir;
+        const double p = ph.gm1 * (qq[4] - 0.5 * m2 * ir);
+        val[1] = fmax(val[1], sqrt(m2) * ir + sqrt(ph.gamma * p * ir));
+        val[2] = fmin(val[2], qq[0]);
+        for (int v = 0; v < 5; ++v) val[3 + v] += wq * qq[v];
+    }
+    for (int c = 0; c < 8; ++c) red[c][t] = val[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] += red[0][t + w];
+            red[1][t] = fmax(red[1][t], red[1][t + w]);
+            red[2][t] = fmin(red[2][t], red[2][t + w]);
+            for (int c = 3; c < 8; ++c) red[c][t] += red[c][t + w];
+        }
+        __syncthreads();
+    }
+    if (t < 8) part[(size_t)e * 8 + t] = red[t][0];
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(int E, double vol_factor, const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+    __shared__ double red[8][256];
+    const int t = threadIdx.x;
+    double val[8] = {0.0, 0.0, 1e300, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = t; e < E; e += 256) {
+        const double* p = part + (size_t)e * 8;
+        val[0] += p[0];
+        val[1] = fmax(val[1], p[1]);
+        val[2] = fmin(val[2], p[2]);
+        for (int c = 3; c < 8; ++c) val[c] += p[c];
+    }
+    for (int c = 0; c < 8; ++c) red[c][t] = val[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] += red[0][t + w];
+            red[1][t] = fmax(red[1][t], red[1][t + w]);
+            red[2][t] = fmin(red[2][t], red[2][t + w]);
+            for (int c = 3; c < 8; ++c) red[c][t] += red[c][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        // vol_factor = J: integrals; KE is the volume mean, J / L^3 folded in by the caller
+        out[0] = red[0][0];
+        out[1] = red[1][0];
+        out[2] = red[2][0];
+        for (int c = 3; c < 8; ++c) out[c] = red[c][0] * vol_factor;
+    }
+}
+
+__global__ void k_scale(double* p, double f) {
+    if (threadIdx.x == 0) p[0] *= f;
+}
+
+// Eq. (9): per-element max |q_v - qref_v| for the three momenta
+__global__ void __launch_bounds__(256) k_err_partial(int E, int NP, const double* __restrict__ q,
+                                                    const double* __restrict__ qr, double* __restrict__ part) {
+    __shared__ double red[3][256];
+    const int e = blockIdx.x;
+    const int t = threadIdx.x;
+    double m[3] = {0.0, 0.0, 0.0};
+    const size_t vs = (size_t)E * NP;
+    for (int n = t; n < NP; n += 256)
+        for (int c = 0; c < 3; ++c) {
+            const size_t idx = (1 + c) * vs + (size_t)e * NP + n;
+            m[c] = fmax(m[c], fabs(q[idx] - qr[idx]));
+        }
+    for (int c = 0; c < 3; ++c) red[c][t] = m[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int c = 0; c < 3; ++c) red[c][t] = fmax(red[c][t], red[c][t + w]);
+        __syncthreads();
+    }
+    if (t < 3) part[(size_t)e * 3 + t] = red[t][0];
+}
+
+__global__ void __launch_bounds__(256) k_err_final(int E, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double red[3][256];
+    const int t = threadIdx.x;
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int e = t; e < E; e += 256)
+        for (int c = 0; c < 3; ++c) m[c] = fmax(m[c], part[(size_t)e * 3 + c]);
+    for (int c = 0; c < 3; ++c) red[c][t] = m[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int c = 0; c < 3; ++c) red[c][t] = fmax(red[c][t], red[c][t + w]);
+        __syncthreads();
+    }
+    if (t < 3) out[t] = red[t][0];
+}
+
+// Filter G: tensor-product 1D projection, one element per block, five variables.
+struct ProjArg {
+    double G[kMaxPP * kMaxPP];   // [PPd][PPs]
+};
+
+template <int PPS, int PPD>
+__global__ void __launch_bounds__(256) k_project(ProjArg pa, int E, const double* __restrict__ src,
+                                                double* __restrict__ dst) {
+    constexpr int NS = PPS * PPS * PPS;
+    constexpr int ND = PPD * PPD * PPD;
+    __shared__ double G[PPD * PPS];
+    __shared__ double a[5 * NS];
+    __shared__ double b1[5 * PPD * PPS * PPS];
+    __shared__ double b2[5 * PPD * PPD * PPS];
+    const int e = blockIdx.x;
+    const int t = threadIdx.x;
+    for (int x = t; x < PPD * PPS; x += 256) G[x] = pa.G[x];
+    const size_t vss = (size_t)E * NS, vsd = (size_t)E * ND;
+    for (int x = t; x < 5 * NS; x += 256) {
+        const int v = x / NS, n = x - v * NS;
+        a[x] = src[v * vss + (size_t)e * NS + n];
+    }
+    __syncthreads();
+    // along x: b1[v][k][j][i'] = sum_i G[i'][i] a[v][k][j][i]
+    for (int x = t; x < 5 * PPS * PPS * PPD; x += 256) {
+        const int ip = x % PPD, r = x / PPD;        // r = (v, k, j)
+        double acc = 0.0;
+        for (int i = 0; i < PPS; ++i) acc += G[ip * PPS + i] * a[r * PPS + i];
+        b1[x] = acc;
+    }
+    __syncthreads();
+    // along y: b2[v][k][j'][i'] = sum_j G[j'][j] b1[v][k][j][i']
+    for (int x = t; x < 5 * PPS * PPD * PPD; x += 256) {
+        const int ip = x % PPD, jp = (x / PPD) % PPD, r = x / (PPD * PPD);   // r = (v, k)
+        double acc = 0.0;
+        for (int j = 0; j < PPS; ++j) acc += G[jp * PPS + j] * b1[(r * PPS + j) * PPD + ip];
+        b2[x] = acc;
+    }
+    __syncthreads();
+    // along z
+    for (int x = t; x < 5 * ND; x += 256) {
+        const int ip = x % PPD, jp = (x / PPD) % PPD, kp = (x / (PPD * PPD)) % PPD, v = x / ND;
+        double acc = 0.0;
+        for (int k = 0; k < PPS; ++k) acc += G[kp * PPS + k] * b2[((v * PPS + k) * PPD + jp) * PPD + ip];
+        dst[v * vsd + (size_t)e * ND + (x - v * ND)] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pack_pairs(int E, int NP, const double* __restrict__ Gq,
+                                                   const double* __restrict__ GR, const double* __restrict__ R3,
+                                                   float* __restrict__ x, float* __restrict__ y) {
+    const size_t total = (size_t)5 * E * NP;
+    const size_t vs = (size_t)E * NP;
+    for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
+        const int v = (int)(idx / vs);
+        const size_t rem = idx - v * vs;
+        const size_t e = rem / NP, n = rem - e * NP;
+        const size_t o = e * (5 * NP) + (size_t)v * NP + n;
+        x[o] = (float)Gq[idx];
+        y[o] = (float)(GR[idx] - R3[idx]);
+    }
+}
+
+__global__ void k_write_descs(SolveDesc d0, SolveDesc d1, int n, SolveDesc* dev) {
+    if (threadIdx.x == 0) {
+        dev[0] = d0;
+        if (n > 1) dev[1] = d1;
+    }
+}
+
+// ------------------------------------------------------------ host launchers
+
+hipError_t upload_basis_tables(const BasisTab* host_tabs) {
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_basis), host_tabs, sizeof(BasisTab) * DG_MAX_ORDER);
+}
+
+hipError_t launch_write_descs(const SolveDesc* host, int n, SolveDesc* dev, hipStream_t st) {
+    if (n < 1 || n > 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_write_descs, dim3(1), dim3(64), 0, st, host[0], n > 1 ? host[1] : host[0], n, dev);
+    return hipGetLastError();
+}
+
+#define DG_DISPATCH_PP(PPV, CALL)           \
+    switch (PPV) {                          \
+        case 2: { constexpr int PP = 2; CALL; } break; \
+        case 3: { constexpr int PP = 3; CALL; } break; \
+        case 4: { constexpr int PP = 4; CALL; } break; \
+        case 5: { constexpr int PP = 5; CALL; } break; \
+        case 6: { constexpr int PP = 6; CALL; } break; \
+        case 7: { constexpr int PP = 7; CALL; } break; \
+        case 8: { constexpr int PP = 8; CALL; } break; \
+        case 9: { constexpr int PP = 9; CALL; } break; \
+        default: return hipErrorInvalidValue;          \
+    }
+
+hipError_t launch_traces(int PPv, const DescList& dl, hipStream_t st) {
+    const int nb = dl.blk[dl.n];
+    DG_DISPATCH_PP(PPv, hipLaunchKernelGGL(k_traces<PP>, dim3(nb), dim3(Shape<PP>::NT), 0, st, dl));
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(int PPv, const DescList& dl, hipStream_t st) {
+    const int nb = dl.blk[dl.n];
+    DG_DISPATCH_PP(PPv, hipLaunchKernelGGL(k_grad<PP>, dim3(nb), dim3(Shape<PP>::NT), 0, st, dl));
+    return hipGetLastError();
+}
+
+hipError_t launch_resid(int PPv, int update, const DescList& dl, double rkA, double rkB, int first_stage,
+                        hipStream_t st) {
+    const int nb = dl.blk[dl.n];
+    if (update) {
+        DG_DISPATCH_PP(PPv, hipLaunchKernelGGL((k_resid<PP, 1>), dim3(nb), dim3(Shape<PP>::NT), 0, st, dl, rkA, rkB,
+                                               first_stage));
+    } else {
+        DG_DISPATCH_PP(PPv, hipLaunchKernelGGL((k_resid<PP, 0>), dim3(nb), dim3(Shape<PP>::NT), 0, st, dl, rkA, rkB,
+                                               first_stage));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tgv(int PPv, const Phys& ph, int N, double* q, hipStream_t st) {
+    DG_DISPATCH_PP(PPv, hipLaunchKernelGGL(k_tgv<PP>, dim3(N * N * N), dim3(Shape<PP>::NT), 0, st, ph, N, q));
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(int PPv, const Phys& ph, int N, const double* q, double* partial, double* out,
+                       hipStream_t st) {
+    const int E = N * N * N;
+    DG_DISPATCH_PP(PPv, hipLaunchKernelGGL(k_diag_partial<PP>, dim3(E), dim3(256), 0, st, ph, E, q, partial));
+    const double J = (ph.h * 0.5) * (ph.h * 0.5) * (ph.h * 0.5);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, E, J, partial, out);
+    hipLaunchKernelGGL(k_scale, dim3(1), dim3(64), 0, st, out, J / (ph.L * ph.L * ph.L));
+    return hipGetLastError();
+}
+
+hipError_t launch_err_inf(int PPv, int E, const double* q, const double* qref, double* partial, double* out,
+                          hipStream_t st) {
+    const int NP = PPv * PPv * PPv;
+    hipLaunchKernelGGL(k_err_partial, dim3(E), dim3(256), 0, st, E, NP, q, qref, partial);
+    hipLaunchKernelGGL(k_err_final, dim3(1), dim3(256), 0, st, E, partial, out);
+    return hipGetLastError();
+}
+
+template <int PPS>
+static hipError_t launch_project_s(int PPd, const ProjArg& pa, int E, const double* src, double* dst, hipStream_t st) {
+    switch (PPd) {
+#define DG_PROJ_CASE(V)                                                                                    \
+    case V:                                                                                                \
+        if constexpr (V <= PPS)                                                                            \
+            hipLaunchKernelGGL((k_project<PPS, V>), dim3(E), dim3(256), 0, st, pa, E, src, dst);           \
+        else                                                                                               \
+            return hipErrorInvalidValue;                                                                   \
+        break;
+        DG_PROJ_CASE(2) DG_PROJ_CASE(3) DG_PROJ_CASE(4) DG_PROJ_CASE(5) DG_PROJ_CASE(6) DG_PROJ_CASE(7)
+        DG_PROJ_CASE(8) DG_PROJ_CASE(9)
+#undef DG_PROJ_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project(int PPs, int PPd, int E, const double* G1, const double* src, double* dst,
+                          hipStream_t st) {
+    ProjArg pa;
+    for (int x = 0; x < PPd * PPs; ++x) pa.G[x] = G1[x];
+    switch (PPs) {
+        case 2: return launch_project_s<2>(PPd, pa, E, src, dst, st);
+        case 3: return launch_project_s<3>(PPd, pa, E, src, dst, st);
+        case 4: return launch_project_s<4>(PPd, pa, E, src, dst, st);
+        case 5: return launch_project_s<5>(PPd, pa, E, src, dst, st);
+        case 6: return launch_project_s<6>(PPd, pa, E, src, dst, st);
+        case 7: return launch_project_s<7>(PPd, pa, E, src, dst, st);
+        case 8: return launch_project_s<8>(PPd, pa, E, src, dst, st);
+        case 9: return launch_project_s<9>(PPd, pa, E, src, dst, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pack_pairs(int E, int n_p, const double* Gq, const double* GR, const double* R3, float* x,
+                             float* y, hipStream_t st) {
+    const size_t total = (size_t)5 * E * n_p;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(k_pack_pairs, dim3(blocks), dim3(256), 0, st, E, n_p, Gq, GR, R3, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace dgnn

@@ -1,0 +1,287 @@
+// C ABI of the forcing network (Sec. 2.1, 2.2): model set-up, inference into a
+// DG residual, and one Adam training step on the MSE loss.
+#include <cmath>
+#include <cstring>
+
+#include "nn_internal.hpp"
+
+namespace dgnn {
+
+#define NN_HIP(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return set_error(DG_EHIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_),        \
+                             __FILE__, __LINE__);                                            \
+    } while (0)
+
+static int pad32(int x) { return (x + 31) / 32 * 32; }
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int layout_dims(const int32_t* dims, int32_t n_layers, int* pd, int64_t* n_params, int64_t* n_bf16,
+                       int64_t* woff, int64_t* boff, int64_t* wbo, int64_t* wtbo) {
+    if (!dims) return set_error(DG_EINVAL, "null dims");
+    if (n_layers < 1 || n_layers > kMaxLayers)
+        return set_error(DG_EINVAL, "n_layers = %d outside [1, %d]", n_layers, kMaxLayers);
+    for (int l = 0; l <= n_layers; ++l) {
+        if (dims[l] < 1 || dims[l] > 1024) return set_error(DG_EINVAL, "dims[%d] = %d outside [1, 1024]", l, dims[l]);
+        pd[l] = pad32(dims[l]);
+    }
+    if (dims[0] % 5 || dims[n_layers] % 5)
+        return set_error(DG_EINVAL, "input and output sizes must be 5 x nodes per element");
+    int64_t np = 0, nb = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        if (woff) woff[l] = np;
+        np += (int64_t)dims[l] * dims[l + 1];
+        if (boff) boff[l] = np;
+        np += dims[l + 1];
+        if (wbo) wbo[l] = nb;
+        nb += (int64_t)pd[l] * pd[l + 1];
+        if (wtbo) wtbo[l] = nb;
+        nb += (int64_t)pd[l] * pd[l + 1];
+    }
+    if (n_params) *n_params = np;
+    if (n_bf16) *n_bf16 = nb;
+    return DG_OK;
+}
+
+NetArgs net_args(const nn_model* m) {
+    NetArgs na;
+    std::memset(&na, 0, sizeof(na));
+    na.n_layers = m->n_layers;
+    na.act = m->act;
+    for (int l = 0; l <= m->n_layers; ++l) {
+        na.dims[l] = m->dims[l];
+        na.pdims[l] = m->pdims[l];
+    }
+    for (int l = 0; l < m->n_layers; ++l) {
+        na.W[l] = m->wbf + m->wbf_off[l];
+        na.WT[l] = m->wbf + m->wtbf_off[l];
+        na.b[l] = m->params + m->boff[l];
+    }
+    for (int v = 0; v < 5; ++v) {
+        na.mu_in[v] = m->norm[v];
+        na.sig_in[v] = m->norm[5 + v];
+        na.mu_out[v] = m->norm[10 + v];
+        na.sig_out[v] = m->norm[15 + v];
+        na.mask[v] = m->mask[v];
+    }
+    return na;
+}
+
+int net_check_mesh(const nn_model* m, const Mesh& mesh) {
+    if (!m) return set_error(DG_EINVAL, "null model");
+    if (m->dims[0] != 5 * mesh.n_p || m->dims[m->n_layers] != 5 * mesh.n_p)
+        return set_error(DG_EINVAL, "network sizes %d -> %d do not match 5 x %d nodes per element", m->dims[0],
+                         m->dims[m->n_layers], mesh.n_p);
+    if (m->device != mesh.device) return set_error(DG_EINVAL, "model and mesh live on different devices");
+    return DG_OK;
+}
+
+int net_forcing_impl(const nn_model* m, const Mesh& mesh, const double* q, double* out, int accumulate,
+                     hipStream_t st) {
+    const NetArgs na = net_args(m);
+    NetTarget tg;
+    tg.q = q;
+    tg.out = out;
+    tg.E = mesh.E;
+    tg.blk_begin = 0;
+    const int nb = (mesh.E + net_rows_per_block() - 1) / net_rows_per_block();
+    if (accumulate) NN_HIP(launch_net_forcing(na, mesh.n_p, &tg, 1, nb, st));
+    else NN_HIP(launch_net_forcing_write(na, mesh.n_p, &tg, 1, nb, st));
+    return DG_OK;
+}
+
+int net_forcing_batch(const nn_model* m, int n_p, const NetTarget* targets, int nt, hipStream_t st) {
+    const NetArgs na = net_args(m);
+    const int rpb = net_rows_per_block();
+    for (int c0 = 0; c0 < nt; c0 += 16) {
+        const int cn = nt - c0 < 16 ? nt - c0 : 16;
+        NetTarget tg[16];
+        int blk = 0;
+        for (int i = 0; i < cn; ++i) {
+            tg[i] = targets[c0 + i];
+            tg[i].blk_begin = blk;
+            blk += (tg[i].E + rpb - 1) / rpb;
+        }
+        NN_HIP(launch_net_forcing_write(na, n_p, tg, cn, blk, st));
+    }
+    return DG_OK;
+}
+
+static int refresh(nn_model* m, hipStream_t st) {
+    const NetArgs na = net_args(m);
+    for (int l = 0; l < m->n_layers; ++l)
+        NN_HIP(launch_net_refresh_layer(na, m->params, m->woff[l], l, m->wbf, m->wbf_off[l], m->wtbf_off[l], st));
+    return DG_OK;
+}
+
+struct TrainLayout {
+    size_t actT[kMaxLayers], dzT[kMaxLayers], part, loss, total;
+    int Bp, nks;
+};
+
+static TrainLayout train_layout(const nn_model* m, int batch) {
+    TrainLayout T;
+    std::memset(&T, 0, sizeof(T));
+    T.Bp = pad32(batch);
+    T.nks = T.Bp / 256;
+    if (T.nks < 1) T.nks = 1;
+    if (T.nks > 16) T.nks = 16;
+    size_t off = 0;
+    size_t maxw = 0;
+    for (int l = 0; l < m->n_layers; ++l) {
+        T.actT[l] = off;
+        off += align256((size_t)m->pdims[l] * T.Bp * sizeof(uint16_t));
+        T.dzT[l] = off;
+        off += align256((size_t)m->pdims[l + 1] * T.Bp * sizeof(uint16_t));
+        const size_t w = (size_t)m->pdims[l] * m->pdims[l + 1];
+        if (w > maxw) maxw = w;
+    }
+    T.part = off;
+    off += align256((size_t)T.nks * maxw * sizeof(float));
+    T.loss = off;
+    off += align256((size_t)(T.Bp / 16 + 1) * sizeof(float));
+    T.total = off;
+    return T;
+}
+
+}  // namespace dgnn
+
+using namespace dgnn;
+
+extern "C" {
+
+int nn_query(const int32_t* dims, int32_t n_layers, int64_t* n_params, int64_t* n_bf16) {
+    int pd[kMaxLayers + 1];
+    return layout_dims(dims, n_layers, pd, n_params, n_bf16, nullptr, nullptr, nullptr, nullptr);
+}
+
+int nn_init(const int32_t* dims, int32_t n_layers, int32_t activation, float* params, uint16_t* w_bf16, float* grad,
+            float* adam_m, float* adam_v, const double* norm, const uint8_t* mask, void* stream, nn_model** out) {
+    if (!out) return set_error(DG_EINVAL, "null output handle");
+    *out = nullptr;
+    if (activation != 0 && activation != 1) return set_error(DG_EINVAL, "activation must be 0 (tanh) or 1 (relu)");
+    if (!params || !w_bf16 || !norm) return set_error(DG_EINVAL, "null params, bf16 buffer or norm");
+    if ((((uintptr_t)params) & 15) || (((uintptr_t)w_bf16) & 255))
+        return set_error(DG_EINVAL, "params must be 16-byte and w_bf16 256-byte aligned");
+    for (int v = 0; v < 5; ++v)
+        if (!(norm[5 + v] > 0) || !(norm[15 + v] > 0) || !std::isfinite(norm[v]) || !std::isfinite(norm[10 + v]))
+            return set_error(DG_EINVAL, "normalisation scales must be positive and finite");
+    nn_model* m = new nn_model;
+    int rc = layout_dims(dims, n_layers, m->pdims, &m->n_params, &m->n_bf16, m->woff, m->boff, m->wbf_off,
+                         m->wtbf_off);
+    if (rc != DG_OK) {
+        delete m;
+        return rc;
+    }
+    m->n_layers = n_layers;
+    m->act = activation;
+    for (int l = 0; l <= n_layers; ++l) m->dims[l] = dims[l];
+    m->params = params;
+    m->wbf = w_bf16;
+    m->grad = grad;
+    m->adam_m = adam_m;
+    m->adam_v = adam_v;
+    std::memcpy(m->norm, norm, sizeof(m->norm));
+    for (int v = 0; v < 5; ++v) m->mask[v] = mask ? (mask[v] ? 1.0 : 0.0) : 1.0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        delete m;
+        return set_error(DG_EHIP, "hipGetDevice failed");
+    }
+    m->device = dev;
+    hipStream_t st = (hipStream_t)stream;
+    if (adam_m && (rc = (launch_fill_f32(adam_m, 0.0f, m->n_params, st) == hipSuccess ? 0 : DG_EHIP))) {
+        delete m;
+        return set_error(rc, "zeroing adam_m failed");
+    }
+    if (adam_v && (rc = (launch_fill_f32(adam_v, 0.0f, m->n_params, st) == hipSuccess ? 0 : DG_EHIP))) {
+        delete m;
+        return set_error(rc, "zeroing adam_v failed");
+    }
+    if ((rc = refresh(m, st)) != DG_OK) {
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return DG_OK;
+}
+
+int nn_refresh(nn_model* m, void* stream) {
+    if (!m) return set_error(DG_EINVAL, "null model");
+    return refresh(m, (hipStream_t)stream);
+}
+
+int nn_set_norm(nn_model* m, const double* norm, const uint8_t* mask) {
+    if (!m || !norm) return set_error(DG_EINVAL, "null model or norm");
+    for (int v = 0; v < 5; ++v)
+        if (!(norm[5 + v] > 0) || !(norm[15 + v] > 0)) return set_error(DG_EINVAL, "normalisation scales must be positive");
+    std::memcpy(m->norm, norm, sizeof(m->norm));
+    if (mask)
+        for (int v = 0; v < 5; ++v) m->mask[v] = mask[v] ? 1.0 : 0.0;
+    return DG_OK;
+}
+
+void nn_free(nn_model* m) { delete m; }
+
+int nn_forcing(const nn_model* m, const dg_mesh* mesh_h, const double* q, double* dqdt, void* ws, size_t ws_bytes,
+               void* stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (!m || !mesh_h) return set_error(DG_EINVAL, "null model or mesh");
+    const Mesh& mesh = mesh_h->m;
+    int rc = net_check_mesh(m, mesh);
+    if (rc) return rc;
+    if (!q || !dqdt || q == dqdt) return set_error(DG_EINVAL, "bad field pointers");
+    return net_forcing_impl(m, mesh, q, dqdt, 1, (hipStream_t)stream);
+}
+
+size_t nn_train_ws(const nn_model* m, int32_t batch) {
+    if (!m || batch < 1) return 0;
+    return train_layout(m, batch).total;
+}
+
+int nn_train_step(nn_model* m, const float* x, const float* y, int32_t batch, float lr, float* loss_dev, void* ws,
+                  size_t ws_bytes, void* stream) {
+    if (!m) return set_error(DG_EINVAL, "null model");
+    if (!m->grad || !m->adam_m || !m->adam_v) return set_error(DG_EINVAL, "model was built without training buffers");
+    if (!x || !y || batch < 1) return set_error(DG_EINVAL, "bad batch");
+    if (!(lr > 0) || !std::isfinite(lr)) return set_error(DG_EINVAL, "learning rate must be positive");
+    if (!ws || (((uintptr_t)ws) & 255)) return set_error(DG_EINVAL, "workspace must be 256-byte aligned");
+    const TrainLayout T = train_layout(m, batch);
+    if (ws_bytes < T.total) return set_error(DG_ENOSPC, "workspace %zu bytes < %zu needed", ws_bytes, T.total);
+    if (train_smem_bytes(net_args(m)) > 160 * 1024 - 2048)
+        return set_error(DG_EINVAL, "network too wide for the on-chip training kernel");
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    const NetArgs na = net_args(m);
+    TrainArgs ta;
+    std::memset(&ta, 0, sizeof(ta));
+    ta.x = x;
+    ta.y = y;
+    ta.B = batch;
+    ta.Bp = T.Bp;
+    ta.grad_scale = (float)(2.0 / ((double)batch * m->dims[m->n_layers]));
+    for (int l = 0; l < m->n_layers; ++l) {
+        ta.actT[l] = (uint16_t*)(base + T.actT[l]);
+        ta.dzT[l] = (uint16_t*)(base + T.dzT[l]);
+    }
+    ta.loss_part = (float*)(base + T.loss);
+    const int nblocks = T.Bp / 16;
+    NN_HIP(launch_train_rows(na, ta, nblocks, st));
+    for (int l = 0; l < m->n_layers; ++l)
+        NN_HIP(launch_wgrad(ta.dzT[l], ta.actT[l], T.Bp, m->pdims[l + 1], m->pdims[l], m->dims[l + 1], m->dims[l],
+                            T.nks, (float*)(base + T.part), m->grad + m->woff[l], m->grad + m->boff[l], st));
+    if (loss_dev)
+        NN_HIP(launch_loss_final(ta.loss_part, nblocks, (float)(1.0 / ((double)batch * m->dims[m->n_layers])),
+                                 loss_dev, st));
+    m->step += 1;
+    const double bc1 = 1.0 - std::pow(0.9, (double)m->step);
+    const double bc2 = 1.0 - std::pow(0.999, (double)m->step);
+    NN_HIP(launch_adam(m->params, m->grad, m->adam_m, m->adam_v, m->n_params, lr, 0.9f, 0.999f, 1e-7f, (float)bc1,
+                       (float)bc2, st));
+    return refresh(m, st);
+}
+
+}  // extern "C"

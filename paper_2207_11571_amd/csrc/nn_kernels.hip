@@ -1,0 +1,450 @@
+// Forcing network kernels for gfx950: bf16 MFMA (v_mfma_f32_16x16x32_bf16)
+// with float32 accumulation.
+//
+// Inference (Sec. 2.2, Eq. (4)): one block of four wavefronts takes 16
+// elements; their states are gathered from the DG layout q[v][e][n],
+// normalised and rounded to bf16 in LDS; every layer is a 16 x N x K product
+// of the LDS-resident activations with the bf16 weights read from L2, with
+// bias and activation fused into the epilogue; the last layer writes the
+// de-normalised forcing straight into the float64 field.  Activations never
+// leave LDS.
+//
+// Training (MSE loss, Adam): the same row blocks run forward, loss and the
+// backward data chain with all activations LDS-resident, and write the
+// transposed activations and output gradients needed by the weight-gradient
+// products dW_l = dz_l^T h_l, which reduce over the batch in a second kernel
+// (split over the batch, then a fixed-order sum).
+#include "dgnn_internal.hpp"
+
+namespace dgnn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRows = 16;      // rows (elements / samples) per block
+constexpr int kThreads = 256;  // four wavefronts
+constexpr int kLdPad = 8;      // LDS row padding (bf16 elements)
+
+int net_rows_per_block() { return kRows; }
+
+// float32 -> bfloat16, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x0040u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ __forceinline__ float act_fwd(float z, int act) { return act == 0 ? tanhf(z) : fmaxf(z, 0.0f); }
+// derivative through the output h = act(z)
+__device__ __forceinline__ float act_bwd(float h, int act) { return act == 0 ? 1.0f - h * h : (h > 0.0f ? 1.0f : 0.0f); }
+
+// C[16][Np] = A[16][Kp] W^T with W [Np][Kp] row-major bf16 in global memory.
+// Wave w computes the 16-column tiles w, w + 4, ...; epi(m, n, value) per output.
+template <class Epi>
+__device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ldA, const uint16_t* __restrict__ W,
+                                         int Kp, int Np, int wave, int lane, Epi epi) {
+    const int kq = 8 * (lane >> 4);
+    const int r = lane & 15;
+    for (int tile = wave; tile < Np / 16; tile += 4) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int n = tile * 16 + r;
+        const uint16_t* wrow = W + (size_t)n * Kp + kq;
+        const uint16_t* arow = sA + r * ldA + kq;
+        for (int k0 = 0; k0 < Kp; k0 += 32) {
+            const bf16x8 a = *(const bf16x8*)(arow + k0);
+            const bf16x8 b = *(const bf16x8*)(wrow + k0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) epi(4 * (lane >> 4) + i, n, acc[i]);
+    }
+}
+
+struct NetTargets {
+    NetTarget t[16];
+    int n;
+};
+
+// ------------------------------------------------------------------ inference
+
+__global__ void __launch_bounds__(kThreads) k_net_forcing(NetArgs na, int NP, NetTargets tg, int accumulate) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
+    int pmax = 0;
+    for (int l = 0; l <= na.n_layers; ++l) pmax = pmax > na.pdims[l] ? pmax : na.pdims[l];
+    const int ld = pmax + kLdPad;
+    uint16_t* bufA = smem;
+    uint16_t* bufB = smem + kRows * ld;
+
+    const int b = blockIdx.x;
+    int ti = 0;
+    for (int i = 1; i < tg.n; ++i)
+        if (tg.t[i].blk_begin <= b) ti = i;
+    const NetTarget T = tg.t[ti];
+    const int e0 = (b - T.blk_begin) * kRows;
+    const int E = T.E;
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    const size_t vs = (size_t)E * NP;
+
+    // gather + normalise + bf16 (zero rows beyond E and columns beyond dims[0])
+    const int din = na.dims[0], pin = na.pdims[0];
+    for (int idx = t; idx < kRows * pin; idx += kThreads) {
+        const int r = idx / pin, c = idx - r * pin;
+        const int e = e0 + r;
+        float x = 0.0f;
+        if (e < E && c < din) {
+            const int v = c / NP, n = c - v * NP;
+            x = (float)((T.q[v * vs + (size_t)e * NP + n] - na.mu_in[v]) / na.sig_in[v]);
+        }
+        bufA[r * ld + c] = f2bf(x);
+    }
+    __syncthreads();
+
+    const int L = na.n_layers;
+    for (int l = 0; l < L; ++l) {
+        const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
+        const float* bias = na.b[l];
+        if (l < L - 1) {
+            const int act = na.act;
+            tile_mma(bufA, ld, na.W[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+                const float z = v + (n < Nd ? bias[n] : 0.0f);
+                bufB[m * ld + n] = f2bf(n < Nd ? act_fwd(z, act) : 0.0f);
+            });
+        } else {
+            tile_mma(bufA, ld, na.W[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+                const int e = e0 + m;
+                if (e < E && n < Nd) {
+                    const float y = v + bias[n];
+                    const int vv = n / NP, node = n - vv * NP;
+                    const double s = na.mask[vv] * (na.sig_out[vv] * (double)y + na.mu_out[vv]);
+                    double* o = T.out + vv * vs + (size_t)e * NP + node;
+                    *o = accumulate ? *o + s : s;
+                }
+            });
+        }
+        __syncthreads();
+        uint16_t* tmp = bufA;
+        bufA = bufB;
+        bufB = tmp;
+    }
+}
+
+// ------------------------------------------------------------------- weights
+
+// bf16 copies of W_l ([pout][pin]) and W_l^T ([pin][pout]), zero padded
+__global__ void __launch_bounds__(256) k_net_refresh(NetArgs na, const float* __restrict__ params,
+                                                    uint16_t* __restrict__ wbf,
+                                                    int64_t woff0, int l, int64_t wbf_off, int64_t wtbf_off) {
+    const int din = na.dims[l], dout = na.dims[l + 1];
+    const int pin = na.pdims[l], pout = na.pdims[l + 1];
+    const int total = pin * pout;
+    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += gridDim.x * 256) {
+        const int o = idx / pin, i = idx - o * pin;
+        const float w = (o < dout && i < din) ? params[woff0 + (int64_t)o * din + i] : 0.0f;
+        const uint16_t h = f2bf(w);
+        wbf[wbf_off + (int64_t)o * pin + i] = h;
+        wbf[wtbf_off + (int64_t)i * pout + o] = h;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fill_f32(float* p, float v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = v;
+}
+
+// ------------------------------------------------------------------- training
+
+// One row block: forward with LDS-resident activations, MSE loss in
+// normalised space, backward data chain dz_{l-1} = (dz_l W_l) * act'(h_l).
+// Writes transposed activations and output gradients for the weight products.
+__global__ void __launch_bounds__(kThreads) k_train_rows(NetArgs na, TrainArgs ta) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
+    const int L = na.n_layers;
+    int pmax = 0;
+    for (int l = 0; l <= L; ++l) pmax = pmax > na.pdims[l] ? pmax : na.pdims[l];
+    const int ld = pmax + kLdPad;
+    // act[0..L-1] then two gradient buffers
+    uint16_t* act[kMaxLayers];
+    for (int l = 0; l < L; ++l) act[l] = smem + l * kRows * ld;
+    uint16_t* g0 = smem + L * kRows * ld;
+    uint16_t* g1 = g0 + kRows * ld;
+    __shared__ float red[kThreads];
+
+    const int r0 = blockIdx.x * kRows;
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    const int B = ta.B, Bp = ta.Bp;
+    const int din = na.dims[0], pin = na.pdims[0];
+    const int npv_in = din / 5;
+    for (int idx = t; idx < kRows * pin; idx += kThreads) {
+        const int r = idx / pin, c = idx - r * pin;
+        const int row = r0 + r;
+        float x = 0.0f;
+        if (row < B && c < din) {
+            const int v = c / npv_in;
+            x = (float)((ta.x[(size_t)row * din + c] - na.mu_in[v]) / na.sig_in[v]);
+        }
+        act[0][r * ld + c] = f2bf(x);
+    }
+    __syncthreads();
+    // forward through the hidden layers
+    for (int l = 0; l < L - 1; ++l) {
+        const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
+        const float* bias = na.b[l];
+        uint16_t* out = act[l + 1];
+        const int a = na.act;
+        tile_mma(act[l], ld, na.W[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+            const float z = v + (n < Nd ? bias[n] : 0.0f);
+            out[m * ld + n] = f2bf(n < Nd ? act_fwd(z, a) : 0.0f);
+        });
+        __syncthreads();
+    }
+    // output layer + loss gradient dY = scale (yhat - ytilde)
+    float lsum = 0.0f;
+    {
+        const int l = L - 1;
+        const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
+        const int npv_out = Nd / 5;
+        const float* bias = na.b[l];
+        tile_mma(act[l], ld, na.W[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+            const int row = r0 + m;
+            float dy = 0.0f;
+            if (row < B && n < Nd) {
+                const int vv = n / npv_out;
+                const float yt = (float)((ta.y[(size_t)row * Nd + n] - na.mu_out[vv]) / na.sig_out[vv]);
+                const float diff = v + bias[n] - yt;
+                lsum += diff * diff;
+                dy = ta.grad_scale * diff;
+            }
+            g0[m * ld + n] = f2bf(dy);
+        });
+    }
+    red[t] = lsum;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) ta.loss_part[blockIdx.x] = red[0];
+    // transposed activations and dz_{L-1}
+    for (int l = 0; l < L; ++l) {
+        const int pd = na.pdims[l];
+        for (int idx = t; idx < pd * kRows; idx += kThreads) {
+            const int c = idx / kRows, r = idx - c * kRows;
+            ta.actT[l][(size_t)c * Bp + r0 + r] = act[l][r * ld + c];
+        }
+    }
+    {
+        const int pd = na.pdims[L];
+        for (int idx = t; idx < pd * kRows; idx += kThreads) {
+            const int c = idx / kRows, r = idx - c * kRows;
+            ta.dzT[L - 1][(size_t)c * Bp + r0 + r] = g0[r * ld + c];
+        }
+    }
+    // backward data chain
+    uint16_t* gin = g0;
+    uint16_t* gout = g1;
+    for (int l = L - 1; l >= 1; --l) {
+        const int Kp = na.pdims[l + 1], Np = na.pdims[l], Nd = na.dims[l];
+        const uint16_t* h = act[l];
+        const int a = na.act;
+        tile_mma(gin, ld, na.WT[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+            const float d = (n < Nd) ? v * act_bwd(bf2f(h[m * ld + n]), a) : 0.0f;
+            gout[m * ld + n] = f2bf(r0 + m < B ? d : 0.0f);
+        });
+        __syncthreads();
+        for (int idx = t; idx < Np * kRows; idx += kThreads) {
+            const int c = idx / kRows, r = idx - c * kRows;
+            ta.dzT[l - 1][(size_t)c * Bp + r0 + r] = gout[r * ld + c];
+        }
+        uint16_t* tmp = gin;
+        gin = gout;
+        gout = tmp;
+        __syncthreads();
+    }
+}
+
+// Weight-gradient partials: part[ks][o][i] = sum over the batch slice ks of
+// dzT[o][b] actT[i][b].  Each wave computes one 16 x 16 tile.
+__global__ void __launch_bounds__(kThreads) k_wgrad(const uint16_t* __restrict__ dzT, const uint16_t* __restrict__ actT,
+                                                   int Bp, int pout, int pin, int kchunk, float* __restrict__ part) {
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    const int tiles_i = pin / 16;
+    const int tile = blockIdx.x * 4 + wave;
+    const int ntiles = (pout / 16) * tiles_i;
+    if (tile >= ntiles) return;
+    const int to = tile / tiles_i, tii = tile - to * tiles_i;
+    const int ks = blockIdx.y;
+    const int kb = ks * kchunk;
+    const int ke = kb + kchunk < Bp ? kb + kchunk : Bp;
+    const int r = lane & 15, kq = 8 * (lane >> 4);
+    const uint16_t* arow = dzT + (size_t)(to * 16 + r) * Bp + kq;
+    const uint16_t* brow = actT + (size_t)(tii * 16 + r) * Bp + kq;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+        const bf16x8 a = *(const bf16x8*)(arow + k0);
+        const bf16x8 b = *(const bf16x8*)(brow + k0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    float* o = part + (size_t)ks * pout * pin;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[(size_t)(to * 16 + 4 * (lane >> 4) + i) * pin + tii * 16 + r] = acc[i];
+}
+
+// grad W_l = sum of the partials (fixed order); grad b_l = row sums of dz_l
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ part, int nks, int pout, int pin,
+                                                     int dout, int din, float* __restrict__ gW) {
+    const int total = dout * din;
+    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += gridDim.x * 256) {
+        const int o = idx / din, i = idx - o * din;
+        float s = 0.0f;
+        for (int k = 0; k < nks; ++k) s += part[(size_t)k * pout * pin + (size_t)o * pin + i];
+        gW[idx] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bias_grad(const uint16_t* __restrict__ dzT, int Bp, int dout,
+                                                  float* __restrict__ gb) {
+    __shared__ float red[256];
+    const int o = blockIdx.x;
+    const int t = threadIdx.x;
+    float s = 0.0f;
+    if (o < dout)
+        for (int b = t; b < Bp; b += 256) s += bf2f(dzT[(size_t)o * Bp + b]);
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0 && o < dout) gb[o] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_loss_final(const float* __restrict__ part, int n, float inv_count,
+                                                   float* __restrict__ loss) {
+    __shared__ float red[256];
+    const int t = threadIdx.x;
+    float s = 0.0f;
+    for (int i = t; i < n; i += 256) s += part[i];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) loss[0] = red[0] * inv_count;
+}
+
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                             float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                                             float bc1, float bc2) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    }
+}
+
+// ------------------------------------------------------------ host launchers
+
+static size_t net_smem_bytes(const NetArgs& na, int nbuf) {
+    int pmax = 0;
+    for (int l = 0; l <= na.n_layers; ++l) pmax = pmax > na.pdims[l] ? pmax : na.pdims[l];
+    return (size_t)nbuf * kRows * (pmax + kLdPad) * sizeof(uint16_t);
+}
+
+hipError_t launch_net_forcing(const NetArgs& na, int n_p, const NetTarget* targets, int nt, int nblocks,
+                              hipStream_t st) {
+    if (nt < 1 || nt > 16) return hipErrorInvalidValue;
+    NetTargets tg;
+    for (int i = 0; i < nt; ++i) tg.t[i] = targets[i];
+    tg.n = nt;
+    const size_t smem = net_smem_bytes(na, 2);
+    if (smem > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_net_forcing, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_net_forcing, dim3(nblocks), dim3(kThreads), smem, st, na, n_p, tg, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_forcing_write(const NetArgs& na, int n_p, const NetTarget* targets, int nt, int nblocks,
+                                    hipStream_t st) {
+    if (nt < 1 || nt > 16) return hipErrorInvalidValue;
+    NetTargets tg;
+    for (int i = 0; i < nt; ++i) tg.t[i] = targets[i];
+    tg.n = nt;
+    const size_t smem = net_smem_bytes(na, 2);
+    if (smem > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_net_forcing, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_net_forcing, dim3(nblocks), dim3(kThreads), smem, st, na, n_p, tg, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_refresh_layer(const NetArgs& na, const float* params, int64_t woff, int l, uint16_t* wbf,
+                                    int64_t wbf_off, int64_t wtbf_off, hipStream_t st) {
+    const int total = na.pdims[l] * na.pdims[l + 1];
+    int blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_net_refresh, dim3(blocks), dim3(256), 0, st, na, params, wbf, woff, l, wbf_off,
+                       wtbf_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st) {
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+size_t train_smem_bytes(const NetArgs& na) { return net_smem_bytes(na, na.n_layers + 2); }
+
+hipError_t launch_train_rows(const NetArgs& na, const TrainArgs& ta, int nblocks, hipStream_t st) {
+    const size_t smem = train_smem_bytes(na);
+    if (smem > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_train_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_train_rows, dim3(nblocks), dim3(kThreads), train_smem_bytes(na), st, na, ta);
+    return hipGetLastError();
+}
+
+hipError_t launch_wgrad(const uint16_t* dzT, const uint16_t* actT, int Bp, int pout, int pin, int dout, int din,
+                        int nks, float* part, float* gW, float* gb, hipStream_t st) {
+    const int ntiles = (pout / 16) * (pin / 16);
+    const int kchunk = ((Bp + nks - 1) / nks + 31) / 32 * 32;
+    hipLaunchKernelGGL(k_wgrad, dim3((ntiles + 3) / 4, nks), dim3(kThreads), 0, st, dzT, actT, Bp, pout, pin,
+                       kchunk, part);
+    int blocks = (dout * din + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks), dim3(256), 0, st, part, nks, pout, pin, dout, din, gW);
+    hipLaunchKernelGGL(k_bias_grad, dim3(dout), dim3(256), 0, st, dzT, Bp, dout, gb);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_final(const float* part, int n, float inv_count, float* loss, hipStream_t st) {
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, n, inv_count, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2, hipStream_t st) {
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, st, params, grad, m, v, n, lr, b1, b2, eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+}  // namespace dgnn

@@ -1,0 +1,523 @@
+// Continuous-batching server of Taylor-Green solves on one GPU.
+//
+// Admission: a request is admitted when a slot is free and a first-fit block
+// of the caller's arena holds its footprint (state, Runge-Kutta register,
+// face-trace / interface-flux / forcing workspace, descriptors, a device ring
+// of kinetic-energy records).  Admitted solves stay resident until done.
+//
+// Execution: one host thread owns one stream.  Each round it admits what fits,
+// then advances every running solve by up to kChunk Runge-Kutta steps; within
+// a step, the stages of all running solves of the same order run in shared
+// launches (one k_grad, one batched network launch for the corrected solves,
+// one k_resid per stage), so requests that arrive while others run join them
+// at the next round.  Per-solve time steps and step counts are independent;
+// nothing is reduced across solves, so each result is what the solve computes
+// alone.  After each round the stream is synchronised once: kinetic-energy
+// records are collected, non-finite solves are failed, finished solves are
+// copied out and their arena blocks released.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "nn_internal.hpp"
+
+namespace dgnn {
+
+constexpr int kHist = 64;    // device KE records per solve between synchronisations
+constexpr int kChunk = 16;   // steps per round
+constexpr size_t kDiagDoubles = 8;
+
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Foot {
+    size_t q, k, ws, desc, hist, total;
+};
+
+static Foot foot(const Mesh& m) {
+    Foot f;
+    const size_t field = a256((size_t)5 * m.E * m.n_p * sizeof(double));
+    f.q = 0;
+    f.k = field;
+    f.ws = 2 * field;
+    f.desc = f.ws + a256(ws_layout(m).total);
+    f.hist = f.desc + a256(2 * sizeof(SolveDesc));
+    f.total = f.hist + a256(kHist * kDiagDoubles * sizeof(double));
+    return f;
+}
+
+static dg_params request_params(const solve_request& r) {
+    dg_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.N = r.N;
+    p.P = r.P;
+    p.viscous = 1;
+    p.L = 2.0 * M_PI;
+    p.Re = r.Re;
+    p.Mach = r.Mach > 0 ? r.Mach : 0.1;
+    p.gamma = 1.4;
+    p.Pr = 0.72;
+    p.Cs = r.Cs;
+    p.Pr_t = 0.6;
+    p.p_ref = 1.0 / (p.gamma * p.Mach * p.Mach);
+    return p;
+}
+
+struct Solve {
+    uint64_t id = 0;
+    solve_request req;
+    Mesh mesh;
+    int state = SOLVE_QUEUED;
+    int error = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    std::atomic<int64_t> steps{0};
+    int64_t n_steps = 0;
+    double dt = 0;
+    size_t off = 0, bytes = 0;
+    double* q = nullptr;
+    double* k = nullptr;
+    char* ws = nullptr;
+    SolveDesc* ddesc = nullptr;
+    double* hist = nullptr;
+    int par = 0;
+    std::vector<double> pending_t;   // times of device records not yet collected
+    std::vector<double> ke;          // collected (t, KE) pairs
+    std::atomic<bool> inject{false};
+};
+
+// first-fit allocator over [0, size) with coalescing
+class Arena {
+  public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t n, size_t& off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                off = it->first;
+                const size_t rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> free_;
+};
+
+}  // namespace dgnn
+
+using namespace dgnn;
+
+struct solve_server {
+    char* base = nullptr;
+    size_t bytes = 0;
+    int max_slots = 0;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::map<uint64_t, std::unique_ptr<Solve>> solves;
+    std::deque<Solve*> queue;
+    std::vector<Solve*> running;
+    uint64_t next_id = 1;
+    bool stop = false;
+    std::thread th;
+    hipStream_t st = nullptr;
+    Arena arena;
+    double busy = 0.0;
+    int64_t batches = 0;
+    double* pinned = nullptr;
+};
+
+namespace dgnn {
+
+static void fail(solve_server* S, Solve* s, int code) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    s->state = SOLVE_FAILED;
+    s->error = code;
+    s->t_done = now_s();
+    S->arena.release(s->off, s->bytes);
+}
+
+// set up one admitted solve: pointers, TGV state, dt, descriptors, traces
+static int admit_one(solve_server* S, Solve* s) {
+    const dg_params prm = request_params(s->req);
+    int rc = make_mesh(&prm, s->mesh);
+    if (rc) return rc;
+    const Foot f = foot(s->mesh);
+    char* p = S->base + s->off;
+    s->q = (double*)(p + f.q);
+    s->k = (double*)(p + f.k);
+    s->ws = p + f.ws;
+    s->ddesc = (SolveDesc*)(p + f.desc);
+    s->hist = (double*)(p + f.hist);
+    if ((rc = init_tgv_impl(s->mesh, s->q, S->st))) return rc;
+    double* dout = s->hist;   // scratch for the time-step diagnostics
+    if ((rc = diag_impl(s->mesh, s->q, dout, s->ws, S->st))) return rc;
+    double h[kDiagDoubles];
+    if (hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, S->st) != hipSuccess ||
+        hipStreamSynchronize(S->st) != hipSuccess)
+        return set_error(DG_EHIP, "admission readback failed");
+    const double dt0 = stable_dt_from_diag(s->mesh, h, 0.4);
+    if (!(dt0 > 0) || !std::isfinite(dt0)) return set_error(DG_ENONFINITE, "bad initial state");
+    s->n_steps = (int64_t)std::ceil(s->req.t_end / dt0 - 1e-12);
+    if (s->n_steps < 1) s->n_steps = 1;
+    s->dt = s->req.t_end / s->n_steps;
+    const WsLayout L = ws_layout(s->mesh);
+    SolveDesc d[2];
+    for (int par = 0; par < 2; ++par) {
+        std::memset(&d[par], 0, sizeof(SolveDesc));
+        d[par].q = s->q;
+        d[par].k = s->k;
+        d[par].forcing = s->req.use_nn ? (const double*)(s->ws + L.forcing) : nullptr;
+        d[par].qtr_in = (const double*)(s->ws + (par == 0 ? L.qtr0 : L.qtr1));
+        d[par].qtr_out = (double*)(s->ws + (par == 0 ? L.qtr1 : L.qtr0));
+        d[par].fv = (double*)(s->ws + L.fv);
+        d[par].N = s->mesh.N;
+        d[par].E = s->mesh.E;
+        d[par].dt = s->dt;
+        d[par].ph = s->mesh.ph;
+    }
+    if (launch_write_descs(d, 2, s->ddesc, S->st) != hipSuccess) return set_error(DG_EHIP, "descriptor upload failed");
+    if (launch_traces(s->mesh.PP, single_list(s->ddesc + 1, s->mesh.E), S->st) != hipSuccess)
+        return set_error(DG_EHIP, "trace launch failed");
+    // record KE(0)
+    if ((rc = diag_impl(s->mesh, s->q, s->hist, s->ws, S->st))) return rc;
+    s->pending_t.push_back(0.0);
+    s->par = 0;
+    s->steps = 0;
+    return DG_OK;
+}
+
+// one Runge-Kutta step of every running solve, stages batched per order
+static int step_all(solve_server* S, std::vector<Solve*>& run) {
+    std::map<int, std::vector<Solve*>> groups;
+    for (Solve* s : run) groups[s->mesh.PP].push_back(s);
+    for (auto& g : groups) {
+        const int PP = g.first;
+        std::vector<Solve*>& v = g.second;
+        for (Solve* s : v)
+            if (s->inject) {
+                static const double nan_val = std::nan("");
+                if (hipMemcpyAsync(s->q, &nan_val, sizeof(double), hipMemcpyHostToDevice, S->st) != hipSuccess)
+                    return set_error(DG_EHIP, "inject failed");
+                if (hipStreamSynchronize(S->st) != hipSuccess) return set_error(DG_EHIP, "inject sync failed");
+                s->inject = false;
+            }
+        for (int stg = 0; stg < 3; ++stg) {
+            for (size_t c0 = 0; c0 < v.size(); c0 += kMaxDescs) {
+                const size_t cn = std::min((size_t)kMaxDescs, v.size() - c0);
+                DescList dl;
+                std::memset(&dl, 0, sizeof(dl));
+                int blk = 0;
+                for (size_t i = 0; i < cn; ++i) {
+                    Solve* s = v[c0 + i];
+                    dl.d[i] = s->ddesc + s->par;
+                    dl.blk[i] = blk;
+                    blk += s->mesh.E;
+                }
+                dl.blk[cn] = blk;
+                dl.n = (int)cn;
+                if (launch_grad(PP, dl, S->st) != hipSuccess) return set_error(DG_EHIP, "grad launch failed");
+                // network forcing of the corrected solves, grouped by model
+                std::map<const nn_model*, std::vector<NetTarget>> nets;
+                for (size_t i = 0; i < cn; ++i) {
+                    Solve* s = v[c0 + i];
+                    if (!s->req.use_nn) continue;
+                    NetTarget t;
+                    t.q = s->q;
+                    t.out = (double*)(s->ws + ws_layout(s->mesh).forcing);
+                    t.E = s->mesh.E;
+                    t.blk_begin = 0;
+                    nets[s->req.model].push_back(t);
+                }
+                for (auto& nt : nets) {
+                    int rc = net_forcing_batch(nt.first, PP * PP * PP, nt.second.data(), (int)nt.second.size(), S->st);
+                    if (rc) return rc;
+                }
+                if (launch_resid(PP, 1, dl, kRkA[stg], kRkB[stg], stg == 0, S->st) != hipSuccess)
+                    return set_error(DG_EHIP, "resid launch failed");
+            }
+            for (Solve* s : v) s->par ^= 1;
+        }
+        for (Solve* s : v) {
+            s->steps.fetch_add(1);
+            if (s->steps % s->req.ke_every == 0 || s->steps == s->n_steps) {
+                if ((int)s->pending_t.size() >= kHist) continue;
+                int rc = diag_impl(s->mesh, s->q, s->hist + kDiagDoubles * s->pending_t.size(), s->ws, S->st);
+                if (rc) return rc;
+                s->pending_t.push_back(s->steps * s->dt);
+            }
+        }
+    }
+    return DG_OK;
+}
+
+static void collect(solve_server* S, Solve* s) {
+    const size_t n = s->pending_t.size();
+    if (n == 0) return;
+    if (hipMemcpy(S->pinned, s->hist, n * kDiagDoubles * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        s->error = DG_EHIP;
+        return;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t r = 0; r < n; ++r) {
+        const double* rec = S->pinned + r * kDiagDoubles;
+        bool finite = std::isfinite(rec[0]);
+        for (int c = 3; c < 8; ++c) finite = finite && std::isfinite(rec[c]);
+        if (!finite) s->error = DG_ENONFINITE;
+        s->ke.push_back(s->pending_t[r]);
+        s->ke.push_back(rec[0]);
+    }
+    s->pending_t.clear();
+}
+
+static void finish(solve_server* S, Solve* s) {
+    if (s->req.q_out_host)
+        hipMemcpy(s->req.q_out_host, s->q, (size_t)5 * s->mesh.E * s->mesh.n_p * sizeof(double), hipMemcpyDeviceToHost);
+    if (s->req.ke_host) {
+        const size_t pairs = std::min((size_t)s->req.ke_capacity, s->ke.size() / 2);
+        std::memcpy(s->req.ke_host, s->ke.data(), pairs * 2 * sizeof(double));
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    s->state = SOLVE_DONE;
+    s->t_done = now_s();
+    S->arena.release(s->off, s->bytes);
+}
+
+static void server_loop(solve_server* S) {
+    hipSetDevice(S->device);
+    std::vector<Solve*> run;
+    while (true) {
+        std::vector<Solve*> admitted;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !run.empty(); });
+            if (S->stop) break;
+            for (auto it = S->queue.begin(); it != S->queue.end();) {
+                Solve* s = *it;
+                if ((int)(run.size() + admitted.size()) >= S->max_slots) break;
+                size_t off;
+                if (S->arena.alloc(s->bytes, off)) {
+                    s->off = off;
+                    s->state = SOLVE_RUNNING;
+                    s->t_admit = now_s();
+                    admitted.push_back(s);
+                    it = S->queue.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        for (Solve* s : admitted) {
+            int rc = admit_one(S, s);
+            if (rc) fail(S, s, rc);
+            else run.push_back(s);
+        }
+        if (run.empty()) {
+            S->cv.notify_all();
+            continue;
+        }
+        int64_t chunk = kChunk;
+        for (Solve* s : run) chunk = std::min(chunk, s->n_steps - s->steps);
+        const double t0 = now_s();
+        int rc = DG_OK;
+        for (int64_t n = 0; n < chunk && rc == DG_OK; ++n) rc = step_all(S, run);
+        hipStreamSynchronize(S->st);
+        const double t1 = now_s();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->busy += t1 - t0;
+            S->batches += chunk;
+        }
+        std::vector<Solve*> keep;
+        for (Solve* s : run) {
+            collect(S, s);
+            int err;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (rc != DG_OK) s->error = rc;
+                err = s->error;
+            }
+            if (err) fail(S, s, err);
+            else if (s->steps >= s->n_steps) finish(S, s);
+            else keep.push_back(s);
+        }
+        run.swap(keep);
+        S->cv.notify_all();
+    }
+    S->cv.notify_all();
+}
+
+}  // namespace dgnn
+
+extern "C" {
+
+size_t solve_footprint(int32_t P, int32_t N, int32_t use_nn) {
+    (void)use_nn;
+    if (P < DG_MIN_ORDER || P > DG_MAX_ORDER || N < 1 || N > 1024) return 0;
+    Mesh m;
+    std::memset(&m, 0, sizeof(m));
+    m.N = N;
+    m.P = P;
+    m.PP = P + 1;
+    m.E = N * N * N;
+    m.n_p = m.PP * m.PP * m.PP;
+    m.n_f = m.PP * m.PP;
+    return foot(m).total;
+}
+
+int solve_server_create(void* arena, size_t arena_bytes, int32_t max_slots, solve_server** out) {
+    if (!out) return set_error(DG_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!arena || (((uintptr_t)arena) & 255)) return set_error(DG_EINVAL, "arena must be non-null and 256-byte aligned");
+    if (max_slots < 1 || max_slots > 4096) return set_error(DG_EINVAL, "max_slots outside [1, 4096]");
+    solve_server* S = new solve_server;
+    S->base = (char*)arena;
+    S->bytes = arena_bytes & ~(size_t)255;
+    S->max_slots = max_slots;
+    S->arena.reset(S->bytes);
+    if (hipGetDevice(&S->device) != hipSuccess) {
+        delete S;
+        return set_error(DG_EHIP, "hipGetDevice failed");
+    }
+    if (hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess) {
+        delete S;
+        return set_error(DG_EHIP, "stream creation failed");
+    }
+    if (hipHostMalloc((void**)&S->pinned, kHist * kDiagDoubles * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        hipStreamDestroy(S->st);
+        delete S;
+        return set_error(DG_EHIP, "pinned buffer allocation failed");
+    }
+    S->th = std::thread(server_loop, S);
+    *out = S;
+    return DG_OK;
+}
+
+int solve_submit(solve_server* S, const solve_request* r, uint64_t* id) {
+    if (!S || !r || !id) return set_error(DG_EINVAL, "null argument");
+    if (!(r->Re > 0) || !(r->t_end > 0) || !std::isfinite(r->t_end) || r->ke_every < 1 || r->Cs < 0)
+        return set_error(DG_EINVAL, "invalid request parameters");
+    if (r->ke_host && r->ke_capacity < 0) return set_error(DG_EINVAL, "negative KE capacity");
+    Mesh m;
+    dg_params p = request_params(*r);
+    int rc = make_mesh(&p, m);
+    if (rc) return rc;
+    if (r->use_nn) {
+        if (!r->model) return set_error(DG_EINVAL, "use_nn without a model");
+        if ((rc = net_check_mesh(r->model, m))) return rc;
+    }
+    const size_t need = foot(m).total;
+    if (need > S->bytes) return set_error(DG_ENOSPC, "request needs %zu bytes, arena holds %zu", need, S->bytes);
+    auto s = std::make_unique<Solve>();
+    s->req = *r;
+    s->mesh = m;
+    s->bytes = need;
+    s->t_submit = now_s();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) return set_error(DG_EINVAL, "server is shutting down");
+        s->id = S->next_id++;
+        *id = s->id;
+        S->queue.push_back(s.get());
+        S->solves[s->id] = std::move(s);
+    }
+    S->cv.notify_all();
+    return DG_OK;
+}
+
+int solve_poll(solve_server* S, uint64_t id, solve_status* st) {
+    if (!S || !st) return set_error(DG_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->solves.find(id);
+    if (it == S->solves.end()) return set_error(DG_ENOENT, "unknown request %llu", (unsigned long long)id);
+    const Solve* s = it->second.get();
+    std::memset(st, 0, sizeof(*st));
+    st->state = s->state;
+    st->error = s->error;
+    st->steps = s->steps;
+    st->n_steps = s->n_steps;
+    st->ke_count = (int32_t)std::min((size_t)std::max(0, s->req.ke_capacity), s->ke.size() / 2);
+    st->t = s->steps * s->dt;
+    st->dt = s->dt;
+    st->queue_s = s->state == SOLVE_QUEUED ? 0.0 : s->t_admit - s->t_submit;
+    st->latency_s = (s->state == SOLVE_DONE || s->state == SOLVE_FAILED) ? s->t_done - s->t_submit : 0.0;
+    st->dof_updates = (int64_t)3 * s->steps * s->mesh.E * s->mesh.n_p;
+    return (s->state == SOLVE_DONE || s->state == SOLVE_FAILED) ? DG_OK : DG_EAGAIN;
+}
+
+int solve_server_drain(solve_server* S) {
+    if (!S) return set_error(DG_EINVAL, "null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv.wait(lk, [&] {
+        if (!S->queue.empty()) return false;
+        for (auto& kv : S->solves)
+            if (kv.second->state == SOLVE_RUNNING) return false;
+        return true;
+    });
+    return DG_OK;
+}
+
+int solve_inject_nan(solve_server* S, uint64_t id) {
+    if (!S) return set_error(DG_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->solves.find(id);
+    if (it == S->solves.end()) return set_error(DG_ENOENT, "unknown request");
+    it->second->inject = true;
+    return DG_OK;
+}
+
+int solve_server_stats(solve_server* S, double* busy_s, int64_t* batches) {
+    if (!S) return set_error(DG_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (busy_s) *busy_s = S->busy;
+    if (batches) *batches = S->batches;
+    return DG_OK;
+}
+
+void solve_server_free(solve_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->th.joinable()) S->th.join();
+    hipStreamSynchronize(S->st);
+    hipStreamDestroy(S->st);
+    hipHostFree(S->pinned);
+    delete S;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+"""GPU parity of the forcing network (Sec. 2.2, Eq. (4)) and its training
+(MSE loss, Adam) against the CPU oracle, through the C ABI.
+
+Tolerances: the network runs on bf16 matrix cores with float32 accumulation,
+so the forcing matches the float64 oracle (same bf16 weights) to 1e-2
+relative (L2 over the field), gradients to 1e-2 relative per tensor, and the
+kinetic-energy history of a corrected run to 1e-3 relative.  Weight rounding
+to bf16 is bitwise.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from helpers import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+DIMS = [320, 256, 256, 256, 320]
+# physical-scale normalisation of the randomly initialised network:
+# mu_in, sigma_in, mu_out, sigma_out per conserved variable
+NORM = [1.0, 0.0, 0.0, 0.0, synthetic.TGV_ENERGY_LEVEL,
+        0.01, 1.0, 1.0, 1.0, 1.0,
+        0.0, 0.0, 0.0, 0.0, 0.0,
+        1e-3, 1e-3, 1e-3, 1e-3, 1e-3]
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_11571_amd import binding
+    binding.lib()
+    return binding
+
+
+def _oracle_model(layers, norm=NORM, mask=(1, 1, 1, 1, 1)):
+    from oracle import forcing, mlp
+    params = [(mlp.bf16_round(W), b.astype(np.float64)) for W, b in layers]
+    n = forcing.Normalisation(norm[0:5], norm[5:10], norm[10:15], norm[15:20], mask)
+    return params, n
+
+
+def _to_gpu(a, dtype=np.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def test_bf16_weight_copies_bitwise(B):
+    from oracle import mlp
+    say("bf16 copies")
+    layers = synthetic.mlp_init(DIMS, seed=0)
+    model = B.Model(DIMS, B.pack_params(layers), NORM)
+    torch.cuda.synchronize()
+    wbf = model.wbf.cpu().numpy().view(np.uint16)
+    off = 0
+    for W, _ in layers:
+        out_d, in_d = W.shape
+        pin, pout = (in_d + 31) // 32 * 32, (out_d + 31) // 32 * 32
+        Wb = wbf[off:off + pout * pin].reshape(pout, pin)
+        off += pout * pin
+        WTb = wbf[off:off + pout * pin].reshape(pin, pout)
+        off += pout * pin
+        ref = (mlp.bf16_round(W).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+        assert np.array_equal(Wb[:out_d, :in_d], ref)
+        assert np.array_equal(WTb[:in_d, :out_d], ref.T)
+        assert not Wb[out_d:].any() and not Wb[:, in_d:].any()
+
+
+@pytest.mark.parametrize("N", [16, 3])
+def test_forcing_matches_oracle(B, N):
+    """C3 network (320 -> 256 x 3 tanh -> 320, Gaussian init, seed 0) on a
+    perturbed TGV state; N = 3 leaves a ragged last block of rows."""
+    from oracle import dg, forcing
+    say("forcing", N)
+    layers = synthetic.mlp_init(DIMS, seed=0)
+    params, norm = _oracle_model(layers)
+    prm = dg.Params(N=N, P=3, Re=200.0)
+    q = dg.tgv_initial_condition(prm).copy()
+    q[1:4] += 0.05 * np.random.default_rng(1).standard_normal(q[1:4].shape)
+    qf = dg.to_flat(q)
+    ref = forcing.network_forcing(qf, params, norm)
+    m = B.Mesh(N, 3, 200.0)
+    model = B.Model(DIMS, B.pack_params(layers), NORM, train=False)
+    out = m.field(0.0)
+    B.nn_forcing(model, m, _to_gpu(qf), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    err = rel_l2(got, ref)
+    print("forcing rel L2", err)
+    assert err < 1e-2
+    # accumulation: a second call adds the same forcing again
+    B.nn_forcing(model, m, _to_gpu(qf), out)
+    assert rel_l2(out.cpu().numpy(), 2 * got) < 1e-15
+
+
+def test_corrected_ke_history(B):
+    """P = 3 TGV at Re 200 on 4^3 elements with the network at every stage:
+    kinetic energy over 100 steps matches the oracle to 1e-3."""
+    from oracle import dg, forcing, rk
+    say("corrected KE history")
+    N, P, Re = 4, 3, 200.0
+    layers = synthetic.mlp_init(DIMS, seed=0)
+    params, norm = _oracle_model(layers)
+    prm = dg.Params(N=N, P=P, Re=Re)
+    q0 = dg.tgv_initial_condition(prm)
+    dt = dg.stable_dt(q0, prm)
+    ke_ref = []
+    rk.integrate(q0, dt, 100, lambda qq, t: forcing.corrected_rhs(qq, prm, params, norm),
+                 callback=lambda n, qq: ke_ref.append(dg.kinetic_energy(qq, prm)))
+    m = B.Mesh(N, P, Re)
+    model = B.Model(DIMS, B.pack_params(layers), NORM, train=False)
+    q = _to_gpu(dg.to_flat(q0))
+    k = m.field(0.0)
+    ke = []
+    for n in range(100):
+        B.dg_rk_step(m, q, k, dt, 1, model=model)
+        ke.append(B.dg_diagnostics(m, q)[0].item())
+    ke, ke_ref = np.array(ke), np.array(ke_ref)
+    err = np.max(np.abs(ke - ke_ref) / ke_ref)
+    print("KE history max rel", err)
+    assert err < 1e-3
+    # the network changes the solution: the uncorrected run differs
+    q2 = _to_gpu(dg.to_flat(q0))
+    B.dg_rk_step(m, q2, k, dt, 100)
+    assert abs(B.dg_diagnostics(m, q2)[0].item() - ke[-1]) > 10 * err * ke[-1]
+
+
+@pytest.mark.parametrize("batch", [256, 200])
+def test_train_step_gradients_and_adam(B, batch):
+    from oracle import mlp
+    say("train step", batch)
+    dims = DIMS
+    layers = synthetic.mlp_init(dims, seed=0)
+    layers = [(W, b + 0.01) for W, b in layers]
+    rng = np.random.default_rng(2)
+    x = np.empty((batch, 320), dtype=np.float32)
+    x[:, :64] = 1.0 + 0.01 * rng.standard_normal((batch, 64))
+    x[:, 64:256] = rng.standard_normal((batch, 192))
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((batch, 64))
+    y = (1e-3 * rng.standard_normal((batch, 320))).astype(np.float32)
+    model = B.Model(dims, B.pack_params(layers), NORM)
+    p_before = model.params.cpu().numpy().astype(np.float64)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    B.nn_train_step(model, _to_gpu(x, np.float32), _to_gpu(y, np.float32), lr=1e-3, loss=loss)
+    torch.cuda.synchronize()
+    # oracle gradient at the same (bf16-rounded) weights, on normalised data
+    params, norm = _oracle_model(layers)
+    n_p = 64
+    xh = (x.astype(np.float64) - np.repeat(norm.mu_in, n_p)) / np.repeat(norm.sigma_in, n_p)
+    yt = (y.astype(np.float64) - np.repeat(norm.mu_out, n_p)) / np.repeat(norm.sigma_out, n_p)
+    loss_ref, grads = mlp.mse_loss_and_grads(params, xh, yt)
+    assert abs(loss.item() / loss_ref - 1) < 1e-2
+    g_gpu = B.unpack_params(model.grad.cpu().numpy().astype(np.float64), dims)
+    for l, ((gW, gb), (rW, rb)) in enumerate(zip(g_gpu, grads)):
+        eW, eb = rel_l2(gW, rW), rel_l2(gb, rb)
+        print("layer", l, "grad rel L2", eW, eb)
+        assert eW < 1e-2 and eb < 1e-2
+    # Adam step 1 on the device's own gradient, float64 reference
+    g_flat = model.grad.cpu().numpy().astype(np.float64)
+    m1 = 0.1 * g_flat
+    v1 = 0.001 * g_flat * g_flat
+    ref = p_before - 1e-3 * (m1 / 0.1) / (np.sqrt(v1 / 0.001) + 1e-7)
+    assert np.max(np.abs(model.params.cpu().numpy() - ref)) < 1e-6 * np.max(np.abs(ref))
+
+
+def test_training_reduces_loss(B):
+    say("training loop")
+    dims = DIMS
+    layers = synthetic.mlp_init(dims, seed=0)
+    rng = np.random.default_rng(4)
+    x = np.empty((512, 320), dtype=np.float32)
+    x[:, :64] = 1.0 + 0.01 * rng.standard_normal((512, 64))
+    x[:, 64:256] = rng.standard_normal((512, 192))
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((512, 64))
+    y = (1e-3 * np.tanh(x[:, 64:256].sum(axis=1, keepdims=True) / 10) * np.ones((1, 320))).astype(np.float32)
+    model = B.Model(dims, B.pack_params(layers), NORM)
+    xg, yg = _to_gpu(x, np.float32), _to_gpu(y, np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    losses = []
+    for it in range(60):
+        B.nn_train_step(model, xg, yg, lr=1e-3, loss=loss)
+        losses.append(loss.item())
+    print("loss", losses[0], losses[-1])
+    assert losses[-1] < 0.2 * losses[0]
