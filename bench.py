@@ -1,0 +1,272 @@
+#!/usr/bin/env python3
+"""Throughput of the corrected DGSEM hot path on one MI355X.
+
+Headline (``value``): DOF-updates per second per Runge-Kutta stage of the
+plain P = 6 Taylor-Green solve, Re 1600, Mach 0.1, 16^3 elements, BR1 viscous
+fluxes, FP64, K timed RK3 steps (a step = three stages, each the BR1 gradient
+pass and the residual + stage update).  DOF = E (P+1)^3 nodes; every stage
+updates every DOF once.
+
+Beside it, on the same JSON line: the corrected P = 3 solve with the forcing
+network at every stage (16^3, Re 200), P = 8, the Smagorinsky variants, the
+roofline of the dominant kernel (residual + stage update) from HIP events
+around its launches, a serving sample (p50 / p99 solve latency of the mixed
+Taylor-Green request stream), and the FP64 CPU oracle timed on the host.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 1]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ALG_BYTES_RESID = 160.0      # read + write q and k per node, one stage update
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests of the mixed stream replayed for the latency sample (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short run for rocprofv3 counter passes: a 1 GiB device copy, then 5 steps of each workload")
+    return ap.parse_args()
+
+
+def time_steps(B, torch, mesh, q, k, dt, steps, model=None):
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    B.dg_rk_step(mesh, q, k, dt, steps, model=model)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, start.elapsed_time(stop) / 1e3
+
+
+def solve_case(B, torch, N, P, Re, Cs, steps, warmup, model=None):
+    mesh = B.Mesh(N, P, Re, Cs=Cs)
+    q = mesh.field()
+    B.dg_init_tgv(mesh, q)
+    dt = B.dg_stable_dt(mesh, q)
+    k = mesh.field(0.0)
+    if warmup:
+        B.dg_rk_step(mesh, q, k, dt, warmup, model=model)
+    wall, ev = time_steps(B, torch, mesh, q, k, dt, steps, model)
+    prof = B.dg_profile_steps(mesh, q, k, dt, 5, model=model)
+    nodes = mesh.E * mesh.n_p
+    rate = nodes * 3 * steps / wall
+    d = B.dg_diagnostics(mesh, q).cpu().numpy()
+    return {"N": N, "P": P, "Re": Re, "Cs": Cs, "nodes": nodes, "dt": dt, "steps": steps, "wall_s": wall,
+            "event_s": ev, "dof_updates_per_s": rate, "ms_per_step": 1e3 * wall / steps,
+            "kernel_ms": prof, "ke_end": float(d[0]), "finite": bool(math.isfinite(d[0]))}
+
+
+def net_model(B, synthetic):
+    dims = [320, 256, 256, 256, 320]
+    norm = [1.0, 0.0, 0.0, 0.0, synthetic.TGV_ENERGY_LEVEL, 0.01, 1, 1, 1, 1,
+            0, 0, 0, 0, 0, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3]
+    return B.Model(dims, B.pack_params(synthetic.mlp_init(dims, seed=0)), norm, train=False)
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    pos = (len(xs) - 1) * p / 100.0
+    lo, hi = int(math.floor(pos)), int(math.ceil(pos))
+    return xs[lo] + (xs[hi] - xs[lo]) * (pos - lo)
+
+
+def serving_sample(B, torch, synthetic, n_req):
+    """Replays the first n_req requests of the mixed stream (Poisson arrivals,
+    mean gap 0.5 s, seed 1; Re, order, mesh drawn uniformly; t_end = 2) in real
+    time against the continuous-batching server."""
+    reqs = synthetic.request_stream(64, seed=1)[:n_req]
+    model = net_model(B, synthetic)
+    free = torch.cuda.mem_get_info()[0]
+    arena = int(min(free * 0.6, 64 << 30)) & ~255
+    srv = B.Server(arena, max_slots=64)
+    t0 = time.perf_counter()
+    ids = []
+    for r in reqs:
+        while time.perf_counter() - t0 < r["arrival"] - reqs[0]["arrival"]:
+            time.sleep(0.002)
+        ids.append(srv.submit(Re=r["Re"], P=r["P"], N=r["N"], t_end=r["t_end"], use_nn=r["use_nn"],
+                              model=model if r["use_nn"] else None, ke_every=50))
+    srv.drain()
+    t_all = time.perf_counter() - t0
+    lat, dofs, failed = [], 0, 0
+    for rid in ids:
+        rc, st = srv.poll(rid)
+        if st.state != B.SOLVE_DONE:
+            failed += 1
+            continue
+        lat.append(st.latency_s)
+        dofs += st.dof_updates
+    busy, batches = srv.stats()
+    srv.close()
+    return {"requests": len(reqs), "failed": failed, "p50_latency_s": percentile(lat, 50),
+            "p99_latency_s": percentile(lat, 99), "makespan_s": t_all, "dof_updates_per_s": dofs / t_all,
+            "solves_per_s": len(lat) / t_all, "gpu_busy_fraction": busy / t_all, "step_rounds": batches,
+            "stream": "first %d of 64 requests, seed 1, mean gap 0.5 s, Re in {30,200,1600}, "
+                      "P in {3+NN,6,8}, N in {4,8,16}, t_end 2" % len(reqs)}
+
+
+def cpu_baseline(steps=2):
+    """The FP64 NumPy oracle on the headline workload (16^3, P = 6, Re 1600
+    TGV): `steps` full RK3 steps, timed on the host cores."""
+    import numpy as np
+    from oracle import dg, rk
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    prm = dg.Params(N=16, P=6, Re=1600.0)
+    q = dg.tgv_initial_condition(prm)
+    dt = dg.stable_dt(q, prm)
+    t0 = time.perf_counter()
+    rk.integrate(q, dt, steps, lambda qq, t: dg.residual(qq, prm))
+    t = time.perf_counter() - t0
+    nodes = q[0].size
+    return {"value": nodes * 3 * steps / t, "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full RK3 steps ({3 * steps} residuals) of the 16^3 P=6 Re-1600 TGV, "
+                      f"NumPy float64, {t:.1f} s", "host_cpus": os.cpu_count()}
+
+
+def counter_traffic(kernel_file, tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{tag}_counters.md")
+    if not os.path.exists(path):
+        return None
+    src = open(os.path.join(ROOT, "paper_2207_11571_amd", "csrc", kernel_file), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    rec = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            key, val = line[2:].split(":", 1)
+            rec[key.strip()] = val.strip()
+    if rec.get("source_sha256_16") != sha:
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
+                                   "(the multi-GPU sharding is a design, see the design notes)"}))
+        sys.exit(2)
+    import torch
+    import synthetic
+    from paper_2207_11571_amd import binding as B
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    B.lib()
+
+    if args.profile_pass:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        for (P, Re, Cs) in ((6, 1600.0, 0.0), (8, 1600.0, 0.0)):
+            solve_case(B, torch, 16, P, Re, Cs, 5, 0)
+        solve_case(B, torch, 16, 3, 200.0, 0.0, 5, 0, model=net_model(B, synthetic))
+        log("profile pass done")
+        return
+
+    log("P6 headline")
+    head = solve_case(B, torch, 16, 6, 1600.0, 0.0, args.steps, args.warmup)
+    log("P8")
+    p8 = solve_case(B, torch, 16, 8, 1600.0, 0.0, args.steps, args.warmup)
+    log("LES variants")
+    p6les = solve_case(B, torch, 16, 6, 1600.0, 0.1, args.steps, args.warmup)
+    p8les = solve_case(B, torch, 16, 8, 1600.0, 0.1, args.steps, args.warmup)
+    log("P3 + network")
+    model = net_model(B, synthetic)
+    p3nn = solve_case(B, torch, 16, 3, 200.0, 0.0, args.steps, args.warmup, model=model)
+    p3 = solve_case(B, torch, 16, 3, 200.0, 0.0, args.steps, args.warmup)
+
+    resid_ms = head["kernel_ms"]["resid"]
+    achieved = ALG_BYTES_RESID * head["nodes"] / (resid_ms * 1e-3) / 1e9
+    traffic = counter_traffic("dg_kernels.hip", "k_resid_p6")
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_resid<7,1> (residual + RK stage update, 16^3 P=6)",
+                "algorithmic_bytes_per_launch": ALG_BYTES_RESID * head["nodes"],
+                "mean_launch_ms": resid_ms}
+    stage_alg_frac = head["dof_updates_per_s"] * ALG_BYTES_RESID / (HBM_PEAK_GBS * 1e9)
+
+    serving = None
+    if args.serve_requests > 0:
+        log("serving sample")
+        serving = serving_sample(B, torch, synthetic, args.serve_requests)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        cpu = cpu_baseline()
+
+    # equal physical time: P3+NN vs plain P6 on the same mesh (per-stage rates x dt ratio)
+    t_p3nn = p3nn["ms_per_step"] / p3nn["dt"]
+    t_p6 = head["ms_per_step"] / head["dt"]
+    out = {
+        "metric": "DOF-updates/s per RK stage (P=3+NN vs plain P=6) and p50/p99 solve latency",
+        "value": head["dof_updates_per_s"],
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (analytic Taylor-Green initial state; Gaussian-initialised network, seed 0)",
+        "config": {"workload": "plain DG, TGV Re 1600 Mach 0.1, 16^3 elements, P=6, BR1, no closure, "
+                               "FP64 RK3 (the P=6 half of the throughput configuration)",
+                   "N": 16, "P": 6, "Re": 1600, "nodes": head["nodes"], "dt": head["dt"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stage_algorithmic_hbm_fraction": stage_alg_frac,
+        "p3_nn": {"dof_updates_per_s": p3nn["dof_updates_per_s"], "ms_per_step": p3nn["ms_per_step"],
+                  "kernel_ms": p3nn["kernel_ms"],
+                  "network_share_of_stage": p3nn["kernel_ms"]["net"] / max(1e-12, sum(p3nn["kernel_ms"][k] for k in ("grad", "net", "resid"))),
+                  "workload": "corrected P=3, 16^3, Re 200, 320-256-256-256-320 tanh bf16 network every stage"},
+        "p3_plain": {"dof_updates_per_s": p3["dof_updates_per_s"], "ms_per_step": p3["ms_per_step"]},
+        "p8": {"dof_updates_per_s": p8["dof_updates_per_s"], "ms_per_step": p8["ms_per_step"],
+               "kernel_ms": p8["kernel_ms"],
+               "resid_hbm_alg_GBs": ALG_BYTES_RESID * p8["nodes"] / (p8["kernel_ms"]["resid"] * 1e-3) / 1e9},
+        "p6_les": {"dof_updates_per_s": p6les["dof_updates_per_s"]},
+        "p8_les": {"dof_updates_per_s": p8les["dof_updates_per_s"]},
+        "wall_per_unit_time_s": {"p3_nn": t_p3nn / 1e3, "p6": t_p6 / 1e3, "p6_over_p3nn": t_p6 / t_p3nn},
+        "serving": serving,
+        "kernel_ms_p6": head["kernel_ms"],
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -105,6 +105,14 @@ typedef struct nn_model nn_model;
 int dg_rk_step(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps,
                const nn_model* forcing, void* ws, size_t ws_bytes, void* stream);
 
+/* Measurement twin of dg_rk_step: the same launches, each bracketed by a HIP
+ * event pair on `stream`; out_ms (host, double[4]) receives the mean duration
+ * in milliseconds of one launch of each stage kernel: [0] face traces,
+ * [1] BR1 gradient pass, [2] network forcing (0 without a model),
+ * [3] residual + stage update.  Synchronises `stream`. */
+int dg_profile_steps(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps,
+                     const nn_model* forcing, void* ws, size_t ws_bytes, void* stream, double* out_ms);
+
 /* Diagnostics, written to out_dev (device, double[8]):
  * [0] kinetic energy (volume mean of rho |v|^2 / 2), [1] max over nodes of
  * |v| + c, [2] min density, [3..7] integrals of the five conserved variables.

@@ -59,6 +59,7 @@ SIGNATURES = {
     "dg_init_tgv": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "dg_rk_step": (ctypes.c_int, [_vp, _vp, _vp, _d, _i32, _vp, _vp, _sz, _vp]),
+    "dg_profile_steps": (ctypes.c_int, [_vp, _vp, _vp, _d, _i32, _vp, _vp, _sz, _vp, ctypes.POINTER(_d)]),
     "dg_diagnostics": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "dg_stable_dt": (ctypes.c_int, [_vp, _vp, _d, ctypes.POINTER(_d), _vp, _sz, _vp]),
     "dg_error_inf": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -179,6 +180,14 @@ def dg_rk_step(mesh, q, k, dt, n_steps, model=None, stream=None):
     check(lib().dg_rk_step(mesh.handle, _ptr(q, torch.float64, "q"), _ptr(k, torch.float64, "k"), float(dt),
                            int(n_steps), model.handle if model is not None else None, _ptr(mesh.ws), mesh.ws_bytes,
                            _stream(stream)))
+
+
+def dg_profile_steps(mesh, q, k, dt, n_steps, model=None, stream=None):
+    out = (ctypes.c_double * 4)()
+    check(lib().dg_profile_steps(mesh.handle, _ptr(q, torch.float64, "q"), _ptr(k, torch.float64, "k"), float(dt),
+                                 int(n_steps), model.handle if model is not None else None, _ptr(mesh.ws),
+                                 mesh.ws_bytes, _stream(stream), out))
+    return {"traces": out[0], "grad": out[1], "net": out[2], "resid": out[3]}
 
 
 def dg_diagnostics(mesh, q, out=None, stream=None):

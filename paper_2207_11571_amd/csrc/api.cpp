@@ -382,6 +382,86 @@ int dg_rk_step(const dg_mesh* m, double* q, double* k, double dt, int32_t n_step
     return rk_impl(m->m, q, k, dt, n_steps, forcing, (char*)ws, (hipStream_t)stream);
 }
 
+int dg_profile_steps(const dg_mesh* mh, double* q, double* k, double dt, int32_t n_steps, const nn_model* model,
+                     void* ws_v, size_t ws_bytes, void* stream, double* out_ms) {
+    int rc = check_mesh(mh);
+    if (rc) return rc;
+    if (!q || !k || q == k || !out_ms) return set_error(DG_EINVAL, "bad pointers");
+    if (!(dt > 0) || n_steps < 1) return set_error(DG_EINVAL, "dt must be positive and n_steps >= 1");
+    if ((rc = check_ws(mh->m, ws_v, ws_bytes))) return rc;
+    if (model && (rc = net_check_mesh(model, mh->m))) return rc;
+    const Mesh& m = mh->m;
+    char* ws = (char*)ws_v;
+    hipStream_t st = (hipStream_t)stream;
+    const WsLayout L = ws_layout(m);
+    SolveDesc d[2];
+    for (int p = 0; p < 2; ++p) {
+        d[p] = make_desc(m, ws, L);
+        d[p].q = q;
+        d[p].k = k;
+        d[p].dt = dt;
+        d[p].forcing = model ? (const double*)(ws + L.forcing) : nullptr;
+        d[p].qtr_in = (const double*)(ws + (p == 0 ? L.qtr0 : L.qtr1));
+        d[p].qtr_out = (double*)(ws + (p == 0 ? L.qtr1 : L.qtr0));
+    }
+    SolveDesc* dd = (SolveDesc*)(ws + L.desc);
+    DG_HIP(launch_write_descs(d, 2, dd, st));
+    const DescList dl[2] = {single_list(dd, m.E), single_list(dd + 1, m.E)};
+    const int n_ev = 2 * (1 + 9 * n_steps);
+    std::vector<hipEvent_t> ev(n_ev);
+    for (auto& e : ev) DG_HIP(hipEventCreate(&e));
+    std::vector<int> kind;
+    int ie = 0;
+    auto mark = [&](int kd) -> hipError_t {
+        kind.push_back(kd);
+        return hipEventRecord(ev[ie++], st);
+    };
+    int err = DG_OK;
+    do {
+        if (mark(0) != hipSuccess || launch_traces(m.PP, dl[1], st) != hipSuccess || hipEventRecord(ev[ie++], st) != hipSuccess) {
+            err = set_error(DG_EHIP, "trace launch failed");
+            break;
+        }
+        int par = 0;
+        for (int n = 0; n < n_steps && err == DG_OK; ++n)
+            for (int s = 0; s < 3 && err == DG_OK; ++s) {
+                if (m.ph.viscous) {
+                    if (mark(1) != hipSuccess || launch_grad(m.PP, dl[par], st) != hipSuccess ||
+                        hipEventRecord(ev[ie++], st) != hipSuccess)
+                        err = set_error(DG_EHIP, "grad launch failed");
+                }
+                if (model && err == DG_OK) {
+                    if (mark(2) != hipSuccess) err = set_error(DG_EHIP, "event failed");
+                    else if ((err = net_forcing_impl(model, m, q, (double*)(ws + L.forcing), 0, st)) == DG_OK &&
+                             hipEventRecord(ev[ie++], st) != hipSuccess)
+                        err = set_error(DG_EHIP, "event failed");
+                }
+                if (err == DG_OK && (mark(3) != hipSuccess ||
+                                     launch_resid(m.PP, 1, dl[par], kRkA[s], kRkB[s], s == 0, st) != hipSuccess ||
+                                     hipEventRecord(ev[ie++], st) != hipSuccess))
+                    err = set_error(DG_EHIP, "resid launch failed");
+                par ^= 1;
+            }
+    } while (0);
+    if (err == DG_OK && hipStreamSynchronize(st) != hipSuccess) err = set_error(DG_EHIP, "synchronise failed");
+    double sum[4] = {0, 0, 0, 0};
+    int cnt[4] = {0, 0, 0, 0};
+    if (err == DG_OK)
+        for (size_t i = 0; i < kind.size(); ++i) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess) {
+                err = set_error(DG_EHIP, "event timing failed");
+                break;
+            }
+            sum[kind[i]] += ms;
+            cnt[kind[i]] += 1;
+        }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (err) return err;
+    for (int c = 0; c < 4; ++c) out_ms[c] = cnt[c] ? sum[c] / cnt[c] : 0.0;
+    return DG_OK;
+}
+
 int dg_diagnostics(const dg_mesh* m, const double* q, double* out_dev, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_mesh(m);
     if (rc) return rc;

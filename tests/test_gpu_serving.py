@@ -1,0 +1,127 @@
+"""GPU tests of the continuous-batching solve server (solve_submit /
+solve_poll through the C ABI): each solve computes the same result alone and
+in a mix, admission respects the arena, impossible requests fail at once,
+a non-finite solve fails alone."""
+import time
+
+import numpy as np
+import pytest
+
+import synthetic
+from helpers import say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+DIMS = [320, 256, 256, 256, 320]
+NORM = [1.0, 0.0, 0.0, 0.0, synthetic.TGV_ENERGY_LEVEL, 0.01, 1, 1, 1, 1, 0, 0, 0, 0, 0, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3]
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_11571_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def model(B):
+    return B.Model(DIMS, B.pack_params(synthetic.mlp_init(DIMS, seed=0)), NORM, train=False)
+
+
+def _wait(srv, ids, timeout=120.0):
+    t0 = time.time()
+    out = {}
+    while len(out) < len(ids):
+        for i in ids:
+            if i in out:
+                continue
+            rc, st = srv.poll(i)
+            if rc == 0:
+                out[i] = st
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"solves not finished: {set(ids) - set(out)}")
+        time.sleep(0.01)
+    return out
+
+
+MIX = [
+    dict(Re=200.0, P=3, N=4, use_nn=True),
+    dict(Re=1600.0, P=6, N=4),
+    dict(Re=30.0, P=3, N=8),
+    dict(Re=1600.0, P=8, N=4, Cs=0.1),
+    dict(Re=200.0, P=3, N=8, use_nn=True),
+    dict(Re=30.0, P=6, N=2),
+]
+
+
+def test_alone_equals_mix(B, model):
+    say("serving alone vs mix")
+    t_end = 0.02
+    alone = []
+    for r in MIX:
+        srv = B.Server(256 << 20, max_slots=8)
+        rid = srv.submit(t_end=t_end, model=model if r.get("use_nn") else None, ke_every=1, ke_capacity=4096,
+                         want_state=True, **r)
+        st = _wait(srv, [rid])[rid]
+        assert st.state == B.SOLVE_DONE, st.error
+        ke, q = srv.results(rid)
+        alone.append((q.copy(), ke[:2 * st.ke_count].copy()))
+        srv.close()
+    srv = B.Server(1 << 30, max_slots=16)
+    ids = []
+    for j, r in enumerate(MIX):
+        ids.append(srv.submit(t_end=t_end, model=model if r.get("use_nn") else None, ke_every=1, ke_capacity=4096,
+                              want_state=True, **r))
+        if j == 2:
+            time.sleep(0.05)     # later requests arrive while the first ones run
+    sts = _wait(srv, ids)
+    for rid, (q_alone, ke_alone) in zip(ids, alone):
+        assert sts[rid].state == B.SOLVE_DONE
+        ke, q = srv.results(rid)
+        assert np.array_equal(q, q_alone)
+        assert np.array_equal(ke[:2 * sts[rid].ke_count], ke_alone)
+        assert sts[rid].latency_s > 0
+    busy, batches = srv.stats()
+    assert batches > 0 and busy > 0
+    srv.close()
+
+
+def test_admission_under_small_arena(B):
+    say("serving admission")
+    foot = B.solve_footprint(6, 4)
+    srv = B.Server(foot + (foot // 2), max_slots=8)     # room for one solve at a time
+    ids = [srv.submit(Re=1600.0, P=6, N=4, t_end=0.01) for _ in range(3)]
+    sts = _wait(srv, ids)
+    assert all(s.state == B.SOLVE_DONE for s in sts.values())
+    queued = sorted(s.queue_s for s in sts.values())
+    assert queued[-1] > queued[0]          # later ones waited for a slot
+    with pytest.raises(B.DGError) as ei:
+        srv.submit(Re=1600.0, P=8, N=16, t_end=0.01)     # can never fit
+    assert ei.value.code == B.DG_ENOSPC
+    srv.close()
+
+
+def test_nonfinite_solve_fails_alone(B):
+    say("serving nan injection")
+    srv = B.Server(256 << 20, max_slots=8)
+    bad = srv.submit(Re=200.0, P=3, N=4, t_end=0.5, ke_every=1)
+    good = srv.submit(Re=200.0, P=3, N=4, t_end=0.05, ke_every=1)
+    srv.inject_nan(bad)
+    sts = _wait(srv, [bad, good])
+    assert sts[bad].state == B.SOLVE_FAILED and sts[bad].error == B.DG_ENONFINITE
+    assert sts[good].state == B.SOLVE_DONE
+    srv.close()
+
+
+def test_invalid_requests(B):
+    srv = B.Server(64 << 20, max_slots=2)
+    with pytest.raises(B.DGError):
+        srv.submit(Re=200.0, P=9, N=4, t_end=0.1)
+    with pytest.raises(B.DGError):
+        srv.submit(Re=200.0, P=3, N=4, t_end=0.1, use_nn=True, model=None)
+    with pytest.raises(B.DGError):
+        srv.submit(Re=-1.0, P=3, N=4, t_end=0.1)
+    srv.close()
