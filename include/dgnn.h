@@ -178,14 +178,26 @@ int nn_forcing(const nn_model* model, const dg_mesh* m, const double* q, double*
 size_t nn_train_ws(const nn_model* model, int32_t batch);
 
 /* One Adam step (Kingma-Ba, bias-corrected, beta1 0.9, beta2 0.999, eps 1e-7)
- * of the MSE loss mean((yhat - (y - mu_out)/sigma_out)^2) on the batch
- * x[batch][n_in], y[batch][n_out] (float32 rows in physical units, device).
- * Forward and backward run on bfloat16 matrix cores with float32
- * accumulation; the float32 master weights, grad, adam_m, adam_v are
- * updated in place and the bfloat16 copies refreshed.  loss_dev (device
- * float, may be NULL) receives the batch loss before the update. */
-int nn_train_step(nn_model* model, const float* x, const float* y, int32_t batch, float lr,
-                  float* loss_dev, void* ws, size_t ws_bytes, void* stream);
+ * of the MSE loss mean((yhat - (y - mu_out)/sigma_out)^2) (Sec. 2.1, Table 1:
+ * mean square error) on a batch of training pairs: x[.][n_in], y[.][n_out]
+ * are float32 rows in physical units (device); the batch is rows
+ * idx[0..batch) of them (device int32, each < the caller's row count), or
+ * rows 0..batch-1 when idx is NULL.  Forward and backward run on bfloat16
+ * matrix cores with float32 accumulation; the float32 master weights, grad,
+ * adam_m, adam_v are updated in place and the bfloat16 copies refreshed.
+ * loss_dev (device float, may be NULL) receives the batch loss before the
+ * update. */
+int nn_train_step(nn_model* model, const float* x, const float* y, const int32_t* idx, int32_t batch,
+                  float lr, float* loss_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* Per-variable mean and standard deviation of a training set (rows of
+ * 5 n_p floats, variable-major): out_host receives mu_x[5], sigma_x[5],
+ * mu_y[5], sigma_y[5], the layout nn_init's norm takes; each sigma is
+ * floored at 1e-12 max(1, |mu|).  Two-pass float64 reduction on the device,
+ * fixed order.  Synchronises `stream`; ws must hold nn_stats_ws(rows) bytes. */
+size_t nn_stats_ws(int64_t rows);
+int nn_data_stats(const float* x, const float* y, int64_t rows, int32_t n_p, double* out_host,
+                  void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------- serving */
 

@@ -74,7 +74,9 @@ SIGNATURES = {
     "nn_free": (None, [_vp]),
     "nn_forcing": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "nn_train_ws": (_sz, [_vp, _i32]),
-    "nn_train_step": (ctypes.c_int, [_vp, _vp, _vp, _i32, _f, _vp, _vp, _sz, _vp]),
+    "nn_train_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _f, _vp, _vp, _sz, _vp]),
+    "nn_stats_ws": (_sz, [_i64]),
+    "nn_data_stats": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(_d), _vp, _sz, _vp]),
     "solve_footprint": (_sz, [_i32, _i32, _i32]),
     "solve_server_create": (ctypes.c_int, [_vp, _sz, _i32, ctypes.POINTER(_vp)]),
     "solve_submit": (ctypes.c_int, [_vp, ctypes.POINTER(solve_request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -294,14 +296,27 @@ def nn_forcing(model, mesh, q, dqdt, stream=None):
                            None, 0, _stream(stream)))
 
 
-def nn_train_step(model, x, y, lr=1e-3, loss=None, stream=None):
-    batch = x.shape[0]
+def nn_train_step(model, x, y, lr=1e-3, loss=None, idx=None, stream=None):
+    """One Adam step on rows idx of (x, y) (all rows when idx is None)."""
+    batch = x.shape[0] if idx is None else idx.shape[0]
+    if idx is not None and (idx.dtype != torch.int32 or not idx.is_cuda):
+        raise ValueError("idx must be a device int32 tensor")
     need = lib().nn_train_ws(model.handle, batch)
     if model.train_ws is None or model.train_ws.numel() < need:
         model.train_ws = torch.empty(need, dtype=torch.uint8, device=x.device)
-    check(lib().nn_train_step(model.handle, _ptr(x, torch.float32, "x"), _ptr(y, torch.float32, "y"), batch,
-                              float(lr), _ptr(loss, torch.float32, "loss"), _ptr(model.train_ws),
-                              model.train_ws.numel(), _stream(stream)))
+    check(lib().nn_train_step(model.handle, _ptr(x, torch.float32, "x"), _ptr(y, torch.float32, "y"),
+                              _ptr(idx, torch.int32, "idx"), batch, float(lr), _ptr(loss, torch.float32, "loss"),
+                              _ptr(model.train_ws), model.train_ws.numel(), _stream(stream)))
+
+
+def nn_data_stats(x, y, n_p, stream=None):
+    """[mu_x(5), sigma_x(5), mu_y(5), sigma_y(5)] of a training set."""
+    rows = x.shape[0]
+    ws = torch.empty(lib().nn_stats_ws(rows), dtype=torch.uint8, device=x.device)
+    out = (ctypes.c_double * 20)()
+    check(lib().nn_data_stats(_ptr(x, torch.float32, "x"), _ptr(y, torch.float32, "y"), rows, n_p, out, _ptr(ws),
+                              ws.numel(), _stream(stream)))
+    return list(out)
 
 
 def solve_footprint(P, N, use_nn=False):

@@ -140,8 +140,9 @@ int net_rows_per_block();
 // training: per-row-block forward / loss / backward data chain, then the
 // weight-gradient products reduced over the batch, then Adam
 struct TrainArgs {
-    const float* x;                   // [B][dims[0]]
-    const float* y;                   // [B][dims[L]]
+    const float* x;                   // [rows][dims[0]]
+    const float* y;                   // [rows][dims[L]]
+    const int32_t* idx;               // batch row b is row idx[b] (null: row b)
     int B, Bp;                        // batch, batch rounded up to 32
     float grad_scale;                 // 2 / (B * dims[L])
     uint16_t* actT[kMaxLayers];       // [pdims[l]][Bp]  (act[0] = xhat)
@@ -153,6 +154,8 @@ hipError_t launch_train_rows(const NetArgs& na, const TrainArgs& ta, int nblocks
 hipError_t launch_wgrad(const uint16_t* dzT, const uint16_t* actT, int Bp, int pout, int pin, int dout, int din,
                         int nks, float* part, float* gW, float* gb, hipStream_t st);
 hipError_t launch_loss_final(const float* part, int n, float inv_count, float* loss, hipStream_t st);
+hipError_t launch_data_stats(const float* x, const float* y, int64_t rows, int n_p, double* part, int nblocks,
+                             double* out_dev, hipStream_t st);
 hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t n,
                        float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st);
 

@@ -242,8 +242,8 @@ size_t nn_train_ws(const nn_model* m, int32_t batch) {
     return train_layout(m, batch).total;
 }
 
-int nn_train_step(nn_model* m, const float* x, const float* y, int32_t batch, float lr, float* loss_dev, void* ws,
-                  size_t ws_bytes, void* stream) {
+int nn_train_step(nn_model* m, const float* x, const float* y, const int32_t* idx, int32_t batch, float lr,
+                  float* loss_dev, void* ws, size_t ws_bytes, void* stream) {
     if (!m) return set_error(DG_EINVAL, "null model");
     if (!m->grad || !m->adam_m || !m->adam_v) return set_error(DG_EINVAL, "model was built without training buffers");
     if (!x || !y || batch < 1) return set_error(DG_EINVAL, "bad batch");
@@ -260,6 +260,7 @@ int nn_train_step(nn_model* m, const float* x, const float* y, int32_t batch, fl
     std::memset(&ta, 0, sizeof(ta));
     ta.x = x;
     ta.y = y;
+    ta.idx = idx;
     ta.B = batch;
     ta.Bp = T.Bp;
     ta.grad_scale = (float)(2.0 / ((double)batch * m->dims[m->n_layers]));
@@ -282,6 +283,26 @@ int nn_train_step(nn_model* m, const float* x, const float* y, int32_t batch, fl
     NN_HIP(launch_adam(m->params, m->grad, m->adam_m, m->adam_v, m->n_params, lr, 0.9f, 0.999f, 1e-7f, (float)bc1,
                        (float)bc2, st));
     return refresh(m, st);
+}
+
+size_t nn_stats_ws(int64_t rows) {
+    (void)rows;
+    return align256(1024 * 10 * sizeof(double)) + align256(30 * sizeof(double));
+}
+
+int nn_data_stats(const float* x, const float* y, int64_t rows, int32_t n_p, double* out_host, void* ws,
+                  size_t ws_bytes, void* stream) {
+    if (!x || !y || !out_host || rows < 1 || n_p < 1) return set_error(DG_EINVAL, "bad arguments");
+    if (!ws || (((uintptr_t)ws) & 255)) return set_error(DG_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < nn_stats_ws(rows)) return set_error(DG_ENOSPC, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    double* part = (double*)ws;
+    double* out = (double*)((char*)ws + align256(1024 * 10 * sizeof(double)));
+    int nblocks = (int)(rows < 1024 ? rows : 1024);
+    NN_HIP(launch_data_stats(x, y, rows, n_p, part, nblocks, out, st));
+    NN_HIP(hipMemcpyAsync(out_host, out, 20 * sizeof(double), hipMemcpyDeviceToHost, st));
+    NN_HIP(hipStreamSynchronize(st));
+    return DG_OK;
 }
 
 }  // extern "C"

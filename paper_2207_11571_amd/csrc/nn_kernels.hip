@@ -42,9 +42,60 @@ __device__ __forceinline__ float act_bwd(float h, int act) { return act == 0 ? 1
 
 // C[16][Np] = A[16][Kp] W^T with W [Np][Kp] row-major bf16 in global memory.
 // Wave w computes the 16-column tiles w, w + 4, ...; epi(m, n, value) per output.
+// For the common widths the K loop is unrolled and the weight fragments of
+// the next tile are loaded while the current tile's MFMAs run (the weights
+// come from L2; their latency, not the matrix cores, bounds this product).
+template <int KP, class Epi>
+__device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, int ldA,
+                                               const uint16_t* __restrict__ W, int Np, int wave, int lane, Epi& epi) {
+    constexpr int KS = KP / 32;
+    const int kq = 8 * (lane >> 4);
+    const int r = lane & 15;
+    const uint16_t* arow = sA + r * ldA + kq;
+    const int ntiles = Np / 16;
+    int tile = wave;
+    if (tile >= ntiles) return;
+    bf16x8 b[KS];
+    {
+        const uint16_t* wrow = W + (size_t)(tile * 16 + r) * KP + kq;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) b[s] = *(const bf16x8*)(wrow + 32 * s);
+    }
+    for (; tile < ntiles; tile += 4) {
+        const int next = tile + 4;
+        bf16x8 bn[KS];
+        if (next < ntiles) {
+            const uint16_t* wrow = W + (size_t)(next * 16 + r) * KP + kq;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) bn[s] = *(const bf16x8*)(wrow + 32 * s);
+        }
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const bf16x8 a = *(const bf16x8*)(arow + 32 * s);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], acc, 0, 0, 0);
+        }
+        const int n = tile * 16 + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) epi(4 * (lane >> 4) + i, n, acc[i]);
+        if (next < ntiles) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) b[s] = bn[s];
+        }
+    }
+}
+
 template <class Epi>
 __device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ldA, const uint16_t* __restrict__ W,
                                          int Kp, int Np, int wave, int lane, Epi epi) {
+    if (Kp == 256) {
+        tile_mma_fixed<256>(sA, ldA, W, Np, wave, lane, epi);
+        return;
+    }
+    if (Kp == 320) {
+        tile_mma_fixed<320>(sA, ldA, W, Np, wave, lane, epi);
+        return;
+    }
     const int kq = 8 * (lane >> 4);
     const int r = lane & 15;
     for (int tile = wave; tile < Np / 16; tile += 4) {
@@ -183,7 +234,8 @@ __global__ void __launch_bounds__(kThreads) k_train_rows(NetArgs na, TrainArgs t
         float x = 0.0f;
         if (row < B && c < din) {
             const int v = c / npv_in;
-            x = (float)((ta.x[(size_t)row * din + c] - na.mu_in[v]) / na.sig_in[v]);
+            const size_t src = ta.idx ? (size_t)ta.idx[row] : (size_t)row;
+            x = (float)((ta.x[src * din + c] - na.mu_in[v]) / na.sig_in[v]);
         }
         act[0][r * ld + c] = f2bf(x);
     }
@@ -212,7 +264,8 @@ __global__ void __launch_bounds__(kThreads) k_train_rows(NetArgs na, TrainArgs t
             float dy = 0.0f;
             if (row < B && n < Nd) {
                 const int vv = n / npv_out;
-                const float yt = (float)((ta.y[(size_t)row * Nd + n] - na.mu_out[vv]) / na.sig_out[vv]);
+                const size_t src = ta.idx ? (size_t)ta.idx[row] : (size_t)row;
+                const float yt = (float)((ta.y[src * Nd + n] - na.mu_out[vv]) / na.sig_out[vv]);
                 const float diff = v + bias[n] - yt;
                 lsum += diff * diff;
                 dy = ta.grad_scale * diff;
@@ -350,7 +403,80 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float
     }
 }
 
+// Per-variable statistics of a training set (rows of 5 n_p floats).  Pass 0
+// sums values, pass 1 squared deviations from the pass-0 means; each block
+// reduces a contiguous chunk of rows, the final kernel sums the block
+// partials in order.
+__global__ void __launch_bounds__(256) k_stats_partial(const float* __restrict__ x, const float* __restrict__ y,
+                                                      int64_t rows, int n_p, const double* __restrict__ mean,
+                                                      double* __restrict__ part) {
+    __shared__ double red[10][256];
+    const int t = threadIdx.x;
+    const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < rows ? r0 + per : rows;
+    const int width = 5 * n_p;
+    double acc[10];
+    for (int c = 0; c < 10; ++c) acc[c] = 0.0;
+    for (int64_t r = r0; r < r1; ++r)
+        for (int c = t; c < width; c += 256) {
+            const int v = c / n_p;
+            const double a = x[r * width + c], b = y[r * width + c];
+            if (mean) {
+                const double da = a - mean[v], db = b - mean[5 + v];
+                acc[v] += da * da;
+                acc[5 + v] += db * db;
+            } else {
+                acc[v] += a;
+                acc[5 + v] += b;
+            }
+        }
+    for (int c = 0; c < 10; ++c) red[c][t] = acc[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int c = 0; c < 10; ++c) red[c][t] += red[c][t + w];
+        __syncthreads();
+    }
+    if (t < 10) part[(size_t)blockIdx.x * 10 + t] = red[t][0];
+}
+
+__global__ void k_stats_means(const double* __restrict__ out, double* __restrict__ mean) {
+    const int c = threadIdx.x;
+    if (c < 10) mean[c] = out[10 * (c / 5) + (c % 5)];
+}
+
+// out layout: mu_x[5], sigma_x[5], mu_y[5], sigma_y[5]
+__global__ void k_stats_final(const double* __restrict__ part, int nblocks, double count, int pass,
+                              double* __restrict__ out) {
+    const int c = threadIdx.x;
+    if (c >= 10) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * 10 + c];
+    const int v = c % 5, which = c / 5;          // which: 0 x, 1 y
+    if (pass == 0) {
+        out[10 * which + v] = s / count;
+    } else {
+        const double mu = out[10 * which + v];
+        const double floor_v = 1e-12 * fmax(1.0, fabs(mu));
+        out[10 * which + 5 + v] = fmax(sqrt(s / count), floor_v);
+    }
+}
+
 // ------------------------------------------------------------ host launchers
+
+hipError_t launch_data_stats(const float* x, const float* y, int64_t rows, int n_p, double* part, int nblocks,
+                             double* out, hipStream_t st) {
+    const double count = (double)rows * n_p;
+    hipLaunchKernelGGL(k_stats_partial, dim3(nblocks), dim3(256), 0, st, x, y, rows, n_p, (const double*)nullptr,
+                       part);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, part, nblocks, count, 0, out);
+    // pass 1 needs the means in the layout mean[v] (x) and mean[5 + v] (y): gather them
+    hipLaunchKernelGGL(k_stats_means, dim3(1), dim3(64), 0, st, out, out + 20);
+    hipLaunchKernelGGL(k_stats_partial, dim3(nblocks), dim3(256), 0, st, x, y, rows, n_p, out + 20, part);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, part, nblocks, count, 1, out);
+    return hipGetLastError();
+}
 
 static size_t net_smem_bytes(const NetArgs& na, int nbuf) {
     int pmax = 0;

@@ -182,3 +182,40 @@ def test_training_reduces_loss(B):
         losses.append(loss.item())
     print("loss", losses[0], losses[-1])
     assert losses[-1] < 0.2 * losses[0]
+
+
+def test_data_stats_match_oracle(B):
+    """Per-variable normalisation of a training set (device reduction) vs the
+    oracle's mean / standard deviation."""
+    from oracle import forcing
+    say("data stats")
+    rng = np.random.default_rng(9)
+    rows = 3000
+    x = np.empty((rows, 320), dtype=np.float32)
+    x[:, :64] = 1.0 + 0.02 * rng.standard_normal((rows, 64))
+    x[:, 64:256] = rng.standard_normal((rows, 192))
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((rows, 64))
+    y = (1e-2 * rng.standard_normal((rows, 320))).astype(np.float32)
+    y[:, :64] = 0.0        # a constant variable: its sigma hits the floor
+    got = np.array(B.nn_data_stats(_to_gpu(x, np.float32), _to_gpu(y, np.float32), 64))
+    ref = forcing.normalisation_from_pairs(x, y).as_array()
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)) < 1e-10
+
+
+def test_train_step_row_indices(B):
+    """A step on rows idx of (x, y) equals a step on the gathered rows."""
+    say("train idx")
+    layers = synthetic.mlp_init(DIMS, seed=3)
+    rng = np.random.default_rng(5)
+    x = np.empty((600, 320), dtype=np.float32)
+    x[:, :64] = 1.0
+    x[:, 64:256] = rng.standard_normal((600, 192))
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL
+    y = (1e-3 * rng.standard_normal((600, 320))).astype(np.float32)
+    idx = rng.permutation(600)[:256].astype(np.int32)
+    m1 = B.Model(DIMS, B.pack_params(layers), NORM)
+    m2 = B.Model(DIMS, B.pack_params(layers), NORM)
+    B.nn_train_step(m1, _to_gpu(x, np.float32), _to_gpu(y, np.float32), idx=torch.from_numpy(idx).cuda())
+    B.nn_train_step(m2, _to_gpu(x[idx], np.float32), _to_gpu(y[idx], np.float32))
+    torch.cuda.synchronize()
+    assert torch.equal(m1.params, m2.params) and torch.equal(m1.grad, m2.grad)
