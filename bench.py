@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the mixed stream replayed for the latency sample (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-study", action="store_true",
+                    help="skip the accuracy-time comparison (trained P=3+NN vs plain P=6 on the 8^3 mesh)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for rocprofv3 counter passes: a 1 GiB device copy, then 5 steps of each workload")
     return ap.parse_args()
@@ -224,6 +226,24 @@ def main():
         log("serving sample")
         serving = serving_sample(B, torch, synthetic, args.serve_requests)
 
+    study = None
+    if not args.no_study:
+        log("accuracy-time study (8^3)")
+        from paper_2207_11571_amd import study as st
+        res = st.run_study(N=8, Re=1600.0, t0=4.0, window=0.15, snapshots=100, eval_end=4.45, batch=512,
+                           orders=(5, 6), variants=[("nn", (1, 1, 1, 1, 1), 200, 1e-3)], log=lambda *a: None)
+        runs = res["runs"]
+        study = {"config": "8^3 elements, Re 1600, P=8 reference from t=0; pairs (Eq. 5) every 0.0015 over "
+                           "[4, 4.15]; 200 epochs Adam batch 512; evaluation to t=4.45; e_n = max momentum "
+                           "error vs filtered P=8 (Eq. 9) on the P=3 space",
+                 "training_s": res["training"]["variants"]["nn"]["seconds"],
+                 "reference_p8_s": res["reference"]["seconds_to_t0"] + res["reference"]["seconds_window_and_eval"]}
+        for name in ("P3", "P3+nn", "P5", "P6"):
+            r = runs[name]
+            study[name] = {"mean_e_window": r["mean_e_window"], "mean_e_beyond": r["mean_e_beyond"],
+                           "wall_per_unit_time_s": r["wall_per_unit_time_s"], "dt": r["dt"]}
+        study["p6_wall_over_p3nn"] = runs["P6"]["wall_s"] / runs["P3+nn"]["wall_s"]
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -263,6 +283,7 @@ def main():
         "p8_les": {"dof_updates_per_s": p8les["dof_updates_per_s"]},
         "wall_per_unit_time_s": {"p3_nn": t_p3nn / 1e3, "p6": t_p6 / 1e3, "p6_over_p3nn": t_p6 / t_p3nn},
         "serving": serving,
+        "accuracy_time_8cubed": study,
         "kernel_ms_p6": head["kernel_ms"],
     }
     print(json.dumps(out))

@@ -216,12 +216,24 @@ __device__ __forceinline__ void face_interp(const double* __restrict__ sh, const
     const int a = fn % PP, b = fn / PP;
     const double* bv = (f & 1) ? B.bp : B.bm;
     for (int v = 0; v < NV; ++v) out[v] = 0.0;
+    if constexpr (NV <= 5) {
 #pragma unroll
-    for (int m = 0; m < PP; ++m) {
-        const int n = line_node<PP>(d, a, b, m);
-        const double c = bv[m];
+        for (int m = 0; m < PP; ++m) {
+            const int n = line_node<PP>(d, a, b, m);
+            const double c = bv[m];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) out[v] += c * sh[v * NP + n];
+            for (int v = 0; v < NV; ++v) out[v] += c * sh[v * NP + n];
+        }
+    } else {
+        // wide interpolations (the 12 gradient components): a partial unroll
+        // keeps the loads in flight within the register budget of large blocks
+#pragma unroll 3
+        for (int m = 0; m < PP; ++m) {
+            const int n = line_node<PP>(d, a, b, m);
+            const double c = bv[m];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v] += c * sh[v * NP + n];
+        }
     }
 }
 
