@@ -106,12 +106,22 @@ def serving_sample(B, torch, synthetic, n_req):
     srv = B.Server(arena, max_slots=64)
     t0 = time.perf_counter()
     ids = []
-    for r in reqs:
+    for i, r in enumerate(reqs):
         while time.perf_counter() - t0 < r["arrival"] - reqs[0]["arrival"]:
             time.sleep(0.002)
         ids.append(srv.submit(Re=r["Re"], P=r["P"], N=r["N"], t_end=r["t_end"], use_nn=r["use_nn"],
                               model=model if r["use_nn"] else None, ke_every=50))
-    srv.drain()
+        if i % 8 == 7:
+            log(f"serving: submitted {i + 1}/{len(reqs)} at {time.perf_counter() - t0:.1f} s")
+    last = time.perf_counter()
+    while True:
+        done = sum(1 for rid in ids if srv.poll(rid)[1].state in (B.SOLVE_DONE, B.SOLVE_FAILED))
+        if done == len(ids):
+            break
+        if time.perf_counter() - last > 10.0:
+            log(f"serving: {done}/{len(ids)} solves finished at {time.perf_counter() - t0:.1f} s")
+            last = time.perf_counter()
+        time.sleep(0.01)
     t_all = time.perf_counter() - t0
     lat, dofs, failed = [], 0, 0
     for rid in ids:

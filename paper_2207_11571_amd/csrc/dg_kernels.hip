@@ -265,20 +265,57 @@ __device__ __forceinline__ void weak_deriv(const double* __restrict__ sh, const 
         out[c] = s * (lp * fhat[(fp * NC + c) * NF + fn] - lm * fhat[(fm * NC + c) * NF + fn] - acc[c]);
 }
 
-// q of this thread's node into LDS, then the six face traces to global
 template <int PP>
-__device__ __forceinline__ void write_traces(double* sh, const BasisTab& B, int t, int e, double* __restrict__ out) {
+struct Lines {
+    static constexpr int NF = PP * PP;
+    static constexpr int NLT = 3 * NF;                             // line tasks
+    static constexpr int LPT = (NLT + Shape<PP>::NT - 1) / Shape<PP>::NT;   // tasks per thread
+};
+
+// traces of the nodal field sh[v*NP + n] (v < NV) at both ends of a line
+template <int PP, int NV>
+__device__ __forceinline__ void line_interp(const double* __restrict__ sh, const BasisTab& B, int d, int fn,
+                                            double om[NV], double op[NV]) {
+    constexpr int NP = PP * PP * PP;
+    const int a = fn % PP, b = fn / PP;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        om[v] = 0.0;
+        op[v] = 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < PP; ++m) {
+        const int n = line_node<PP>(d, a, b, m);
+        const double cm = B.bm[m], cp = B.bp[m];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double x = sh[v * NP + n];
+            om[v] += cm * x;
+            op[v] += cp * x;
+        }
+    }
+}
+
+// the six face traces of the nodal state in LDS, to global
+template <int PP>
+__device__ __forceinline__ void write_traces(const double* __restrict__ sh, const BasisTab& B, int t, int e,
+                                             double* __restrict__ out) {
     using S = Shape<PP>;
+    using Ln = Lines<PP>;
 #pragma unroll
-    for (int r = 0; r < S::TPT; ++r) {
+    for (int r = 0; r < Ln::LPT; ++r) {
         const int tau = t + r * S::NT;
-        if (tau < S::NFT) {
-            const int f = tau / S::NF, fn = tau - f * S::NF;
-            double qi[5];
-            face_interp<PP, 5>(sh, B, f, fn, qi);
-            double* o = out + (size_t)(e * 6 + f) * 5 * S::NF + fn;
+        if (tau < Ln::NLT) {
+            const int d = tau / S::NF, fn = tau - d * S::NF;
+            double qm[5], qp[5];
+            line_interp<PP, 5>(sh, B, d, fn, qm, qp);
+            double* om = out + (size_t)(e * 6 + 2 * d) * 5 * S::NF + fn;
+            double* op = om + 5 * S::NF;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) o[v * S::NF] = qi[v];
+            for (int v = 0; v < 5; ++v) {
+                om[v * S::NF] = qm[v];
+                op[v * S::NF] = qp[v];
+            }
         }
     }
 }

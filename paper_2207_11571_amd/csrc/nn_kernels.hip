@@ -1,7 +1,7 @@
 // Forcing network kernels for gfx950: bf16 MFMA (v_mfma_f32_16x16x32_bf16)
 // with float32 accumulation.
 //
-// Inference (Sec. 2.2, Eq. (4)): one block of four wavefronts takes 16
+// Inference (Sec. 2.2, Eq. (4)): one block of eight wavefronts takes 16
 // elements; their states are gathered from the DG layout q[v][e][n],
 // normalised and rounded to bf16 in LDS; every layer is a 16 x N x K product
 // of the LDS-resident activations with the bf16 weights read from L2, with
@@ -22,7 +22,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRows = 16;      // rows (elements / samples) per block
-constexpr int kThreads = 256;  // four wavefronts
+constexpr int kThreads = 256;     // weight-gradient blocks: four wavefronts, one tile each
+constexpr int kRowWaves = 8;      // row-block kernels: eight wavefronts share the column tiles
+constexpr int kRowThreads = 64 * kRowWaves;
 constexpr int kLdPad = 8;      // LDS row padding (bf16 elements)
 
 int net_rows_per_block() { return kRows; }
@@ -61,8 +63,8 @@ __device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, 
 #pragma unroll
         for (int s = 0; s < KS; ++s) b[s] = *(const bf16x8*)(wrow + 32 * s);
     }
-    for (; tile < ntiles; tile += 4) {
-        const int next = tile + 4;
+    for (; tile < ntiles; tile += kRowWaves) {
+        const int next = tile + kRowWaves;
         bf16x8 bn[KS];
         if (next < ntiles) {
             const uint16_t* wrow = W + (size_t)(next * 16 + r) * KP + kq;
@@ -98,7 +100,7 @@ __device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ld
     }
     const int kq = 8 * (lane >> 4);
     const int r = lane & 15;
-    for (int tile = wave; tile < Np / 16; tile += 4) {
+    for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         const int n = tile * 16 + r;
         const uint16_t* wrow = W + (size_t)n * Kp + kq;
@@ -120,7 +122,7 @@ struct NetTargets {
 
 // ------------------------------------------------------------------ inference
 
-__global__ void __launch_bounds__(kThreads) k_net_forcing(NetArgs na, int NP, NetTargets tg, int accumulate) {
+__global__ void __launch_bounds__(kRowThreads) k_net_forcing(NetArgs na, int NP, NetTargets tg, int accumulate) {
     extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
     int pmax = 0;
     for (int l = 0; l <= na.n_layers; ++l) pmax = pmax > na.pdims[l] ? pmax : na.pdims[l];
@@ -141,7 +143,7 @@ __global__ void __launch_bounds__(kThreads) k_net_forcing(NetArgs na, int NP, Ne
 
     // gather + normalise + bf16 (zero rows beyond E and columns beyond dims[0])
     const int din = na.dims[0], pin = na.pdims[0];
-    for (int idx = t; idx < kRows * pin; idx += kThreads) {
+    for (int idx = t; idx < kRows * pin; idx += kRowThreads) {
         const int r = idx / pin, c = idx - r * pin;
         const int e = e0 + r;
         float x = 0.0f;
@@ -209,7 +211,7 @@ __global__ void __launch_bounds__(256) k_fill_f32(float* p, float v, size_t n) {
 // One row block: forward with LDS-resident activations, MSE loss in
 // normalised space, backward data chain dz_{l-1} = (dz_l W_l) * act'(h_l).
 // Writes transposed activations and output gradients for the weight products.
-__global__ void __launch_bounds__(kThreads) k_train_rows(NetArgs na, TrainArgs ta) {
+__global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArgs ta) {
     extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
     const int L = na.n_layers;
     int pmax = 0;
@@ -220,7 +222,7 @@ __global__ void __launch_bounds__(kThreads) k_train_rows(NetArgs na, TrainArgs t
     for (int l = 0; l < L; ++l) act[l] = smem + l * kRows * ld;
     uint16_t* g0 = smem + L * kRows * ld;
     uint16_t* g1 = g0 + kRows * ld;
-    __shared__ float red[kThreads];
+    __shared__ float red[kRowThreads];
 
     const int r0 = blockIdx.x * kRows;
     const int t = threadIdx.x;
@@ -228,7 +230,7 @@ __global__ void __launch_bounds__(kThreads) k_train_rows(NetArgs na, TrainArgs t
     const int B = ta.B, Bp = ta.Bp;
     const int din = na.dims[0], pin = na.pdims[0];
     const int npv_in = din / 5;
-    for (int idx = t; idx < kRows * pin; idx += kThreads) {
+    for (int idx = t; idx < kRows * pin; idx += kRowThreads) {
         const int r = idx / pin, c = idx - r * pin;
         const int row = r0 + r;
         float x = 0.0f;
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(kThreads) k_train_rows(NetArgs na, TrainArgs t
     }
     red[t] = lsum;
     __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
+    for (int w = kRowThreads / 2; w > 0; w >>= 1) {
         if (t < w) red[t] += red[t + w];
         __syncthreads();
     }
@@ -283,14 +285,14 @@ __global__ void __launch_bounds__(kThreads) k_train_rows(NetArgs na, TrainArgs t
     // transposed activations and dz_{L-1}
     for (int l = 0; l < L; ++l) {
         const int pd = na.pdims[l];
-        for (int idx = t; idx < pd * kRows; idx += kThreads) {
+        for (int idx = t; idx < pd * kRows; idx += kRowThreads) {
             const int c = idx / kRows, r = idx - c * kRows;
             ta.actT[l][(size_t)c * Bp + r0 + r] = act[l][r * ld + c];
         }
     }
     {
         const int pd = na.pdims[L];
-        for (int idx = t; idx < pd * kRows; idx += kThreads) {
+        for (int idx = t; idx < pd * kRows; idx += kRowThreads) {
             const int c = idx / kRows, r = idx - c * kRows;
             ta.dzT[L - 1][(size_t)c * Bp + r0 + r] = g0[r * ld + c];
         }
@@ -307,7 +309,7 @@ __global__ void __launch_bounds__(kThreads) k_train_rows(NetArgs na, TrainArgs t
             gout[m * ld + n] = f2bf(r0 + m < B ? d : 0.0f);
         });
         __syncthreads();
-        for (int idx = t; idx < Np * kRows; idx += kThreads) {
+        for (int idx = t; idx < Np * kRows; idx += kRowThreads) {
             const int c = idx / kRows, r = idx - c * kRows;
             ta.dzT[l - 1][(size_t)c * Bp + r0 + r] = gout[r * ld + c];
         }
@@ -496,7 +498,7 @@ hipError_t launch_net_forcing(const NetArgs& na, int n_p, const NetTarget* targe
                                            (int)smem);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_net_forcing, dim3(nblocks), dim3(kThreads), smem, st, na, n_p, tg, 1);
+    hipLaunchKernelGGL(k_net_forcing, dim3(nblocks), dim3(kRowThreads), smem, st, na, n_p, tg, 1);
     return hipGetLastError();
 }
 
@@ -512,7 +514,7 @@ hipError_t launch_net_forcing_write(const NetArgs& na, int n_p, const NetTarget*
                                            (int)smem);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_net_forcing, dim3(nblocks), dim3(kThreads), smem, st, na, n_p, tg, 0);
+    hipLaunchKernelGGL(k_net_forcing, dim3(nblocks), dim3(kRowThreads), smem, st, na, n_p, tg, 0);
     return hipGetLastError();
 }
 
@@ -543,7 +545,7 @@ hipError_t launch_train_rows(const NetArgs& na, const TrainArgs& ta, int nblocks
                                            (int)smem);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_train_rows, dim3(nblocks), dim3(kThreads), train_smem_bytes(na), st, na, ta);
+    hipLaunchKernelGGL(k_train_rows, dim3(nblocks), dim3(kRowThreads), train_smem_bytes(na), st, na, ta);
     return hipGetLastError();
 }
 

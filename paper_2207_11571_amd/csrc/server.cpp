@@ -5,12 +5,14 @@
 // face-trace / interface-flux / forcing workspace, descriptors, a device ring
 // of kinetic-energy records).  Admitted solves stay resident until done.
 //
-// Execution: one host thread owns one stream.  Each round it admits what fits,
-// then advances every running solve by up to kChunk Runge-Kutta steps; within
-// a step, the stages of all running solves of the same order run in shared
-// launches (one k_grad, one batched network launch for the corrected solves,
-// one k_resid per stage), so requests that arrive while others run join them
-// at the next round.  Per-solve time steps and step counts are independent;
+// Execution: one host thread, one stream per polynomial order.  Each round it
+// admits what fits, then advances every running solve by a number of
+// Runge-Kutta steps sized to its order group's cost; within a step, the
+// stages of all running solves of the same order run in shared launches (one
+// k_grad, one batched network launch for the corrected solves, one k_resid
+// per stage) on that order's stream, and the groups of different orders
+// overlap on the device.  Requests that arrive while others run join them at
+// the next round.  Per-solve time steps and step counts are independent;
 // nothing is reduced across solves, so each result is what the solve computes
 // alone.  After each round the stream is synchronised once: kinetic-energy
 // records are collected, non-finite solves are failed, finished solves are
@@ -33,7 +35,8 @@
 namespace dgnn {
 
 constexpr int kHist = 64;    // device KE records per solve between synchronisations
-constexpr int kChunk = 16;   // steps per round
+constexpr int kChunk = 16;   // steps per round of the costliest order group
+constexpr int kChunkMax = 256;  // steps per round of any group
 constexpr size_t kDiagDoubles = 8;
 
 static double now_s() {
@@ -151,7 +154,8 @@ struct solve_server {
     uint64_t next_id = 1;
     bool stop = false;
     std::thread th;
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;                 // admission work
+    hipStream_t gst[dgnn::kMaxPP + 1] = {};   // one stream per order group
     Arena arena;
     double busy = 0.0;
     int64_t batches = 0;
@@ -212,74 +216,96 @@ static int admit_one(solve_server* S, Solve* s) {
         return set_error(DG_EHIP, "trace launch failed");
     // record KE(0)
     if ((rc = diag_impl(s->mesh, s->q, s->hist, s->ws, S->st))) return rc;
+    if (hipStreamSynchronize(S->st) != hipSuccess) return set_error(DG_EHIP, "admission synchronise failed");
     s->pending_t.push_back(0.0);
     s->par = 0;
     s->steps = 0;
     return DG_OK;
 }
 
-// one Runge-Kutta step of every running solve, stages batched per order
-static int step_all(solve_server* S, std::vector<Solve*>& run) {
-    std::map<int, std::vector<Solve*>> groups;
-    for (Solve* s : run) groups[s->mesh.PP].push_back(s);
-    for (auto& g : groups) {
-        const int PP = g.first;
-        std::vector<Solve*>& v = g.second;
-        for (Solve* s : v)
-            if (s->inject) {
-                static const double nan_val = std::nan("");
-                if (hipMemcpyAsync(s->q, &nan_val, sizeof(double), hipMemcpyHostToDevice, S->st) != hipSuccess)
-                    return set_error(DG_EHIP, "inject failed");
-                if (hipStreamSynchronize(S->st) != hipSuccess) return set_error(DG_EHIP, "inject sync failed");
-                s->inject = false;
-            }
-        for (int stg = 0; stg < 3; ++stg) {
-            for (size_t c0 = 0; c0 < v.size(); c0 += kMaxDescs) {
-                const size_t cn = std::min((size_t)kMaxDescs, v.size() - c0);
-                DescList dl;
-                std::memset(&dl, 0, sizeof(dl));
-                int blk = 0;
-                for (size_t i = 0; i < cn; ++i) {
-                    Solve* s = v[c0 + i];
-                    dl.d[i] = s->ddesc + s->par;
-                    dl.blk[i] = blk;
-                    blk += s->mesh.E;
-                }
-                dl.blk[cn] = blk;
-                dl.n = (int)cn;
-                if (launch_grad(PP, dl, S->st) != hipSuccess) return set_error(DG_EHIP, "grad launch failed");
-                // network forcing of the corrected solves, grouped by model
-                std::map<const nn_model*, std::vector<NetTarget>> nets;
-                for (size_t i = 0; i < cn; ++i) {
-                    Solve* s = v[c0 + i];
-                    if (!s->req.use_nn) continue;
-                    NetTarget t;
-                    t.q = s->q;
-                    t.out = (double*)(s->ws + ws_layout(s->mesh).forcing);
-                    t.E = s->mesh.E;
-                    t.blk_begin = 0;
-                    nets[s->req.model].push_back(t);
-                }
-                for (auto& nt : nets) {
-                    int rc = net_forcing_batch(nt.first, PP * PP * PP, nt.second.data(), (int)nt.second.size(), S->st);
-                    if (rc) return rc;
-                }
-                if (launch_resid(PP, 1, dl, kRkA[stg], kRkB[stg], stg == 0, S->st) != hipSuccess)
-                    return set_error(DG_EHIP, "resid launch failed");
-            }
-            for (Solve* s : v) s->par ^= 1;
+// one Runge-Kutta step of every solve of one order group, stages batched,
+// enqueued on the group's stream
+static int step_group(solve_server* S, int PP, std::vector<Solve*>& v, hipStream_t st) {
+    for (Solve* s : v)
+        if (s->inject) {
+            static const double nan_val = std::nan("");
+            if (hipMemcpyAsync(s->q, &nan_val, sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+                return set_error(DG_EHIP, "inject failed");
+            if (hipStreamSynchronize(st) != hipSuccess) return set_error(DG_EHIP, "inject sync failed");
+            s->inject = false;
         }
-        for (Solve* s : v) {
-            s->steps.fetch_add(1);
-            if (s->steps % s->req.ke_every == 0 || s->steps == s->n_steps) {
-                if ((int)s->pending_t.size() >= kHist) continue;
-                int rc = diag_impl(s->mesh, s->q, s->hist + kDiagDoubles * s->pending_t.size(), s->ws, S->st);
-                if (rc) return rc;
-                s->pending_t.push_back(s->steps * s->dt);
+    for (int stg = 0; stg < 3; ++stg) {
+        for (size_t c0 = 0; c0 < v.size(); c0 += kMaxDescs) {
+            const size_t cn = std::min((size_t)kMaxDescs, v.size() - c0);
+            DescList dl;
+            std::memset(&dl, 0, sizeof(dl));
+            int blk = 0;
+            for (size_t i = 0; i < cn; ++i) {
+                Solve* s = v[c0 + i];
+                dl.d[i] = s->ddesc + s->par;
+                dl.blk[i] = blk;
+                blk += s->mesh.E;
             }
+            dl.blk[cn] = blk;
+            dl.n = (int)cn;
+            if (launch_grad(PP, dl, st) != hipSuccess) return set_error(DG_EHIP, "grad launch failed");
+            // network forcing of the corrected solves, grouped by model
+            std::map<const nn_model*, std::vector<NetTarget>> nets;
+            for (size_t i = 0; i < cn; ++i) {
+                Solve* s = v[c0 + i];
+                if (!s->req.use_nn) continue;
+                NetTarget t;
+                t.q = s->q;
+                t.out = (double*)(s->ws + ws_layout(s->mesh).forcing);
+                t.E = s->mesh.E;
+                t.blk_begin = 0;
+                nets[s->req.model].push_back(t);
+            }
+            for (auto& nt : nets) {
+                int rc = net_forcing_batch(nt.first, PP * PP * PP, nt.second.data(), (int)nt.second.size(), st);
+                if (rc) return rc;
+            }
+            if (launch_resid(PP, 1, dl, kRkA[stg], kRkB[stg], stg == 0, st) != hipSuccess)
+                return set_error(DG_EHIP, "resid launch failed");
+        }
+        for (Solve* s : v) s->par ^= 1;
+    }
+    for (Solve* s : v) {
+        s->steps.fetch_add(1);
+        if (s->steps % s->req.ke_every == 0 || s->steps == s->n_steps) {
+            if ((int)s->pending_t.size() >= kHist) continue;
+            int rc = diag_impl(s->mesh, s->q, s->hist + kDiagDoubles * s->pending_t.size(), s->ws, st);
+            if (rc) return rc;
+            s->pending_t.push_back(s->steps * s->dt);
         }
     }
     return DG_OK;
+}
+
+// Steps of one round for each order group: the costliest group (by nodes
+// per step) takes kChunk steps, cheaper groups proportionally more (up to
+// kChunkMax), so that a round takes about the same time on every stream;
+// never past any solve's last step or its KE-record capacity.
+static std::map<int, int64_t> round_plan(const std::map<int, std::vector<Solve*>>& groups) {
+    std::map<int, double> cost;
+    double cmax = 0.0;
+    for (auto& g : groups) {
+        double c = 0.0;
+        for (Solve* s : g.second) c += (double)s->mesh.E * s->mesh.n_p * (s->req.use_nn ? 2.0 : 1.0);
+        cost[g.first] = c;
+        cmax = std::max(cmax, c);
+    }
+    std::map<int, int64_t> plan;
+    for (auto& g : groups) {
+        int64_t n = (int64_t)std::min((double)kChunkMax, std::floor(kChunk * cmax / std::max(1.0, cost[g.first])));
+        n = std::max<int64_t>(n, 1);
+        for (Solve* s : g.second) {
+            n = std::min<int64_t>(n, s->n_steps - s->steps);
+            n = std::min<int64_t>(n, (int64_t)(kHist - 1 - (int)s->pending_t.size()) * s->req.ke_every);
+        }
+        plan[g.first] = std::max<int64_t>(n, 1);
+    }
+    return plan;
 }
 
 static void collect(solve_server* S, Solve* s) {
@@ -304,7 +330,7 @@ static void collect(solve_server* S, Solve* s) {
 
 static void finish(solve_server* S, Solve* s) {
     if (s->req.q_out_host)
-        hipMemcpy(s->req.q_out_host, s->q, (size_t)5 * s->mesh.E * s->mesh.n_p * sizeof(double), hipMemcpyDeviceToHost);
+        (void)hipMemcpy(s->req.q_out_host, s->q, (size_t)5 * s->mesh.E * s->mesh.n_p * sizeof(double), hipMemcpyDeviceToHost);
     if (s->req.ke_host) {
         const size_t pairs = std::min((size_t)s->req.ke_capacity, s->ke.size() / 2);
         std::memcpy(s->req.ke_host, s->ke.data(), pairs * 2 * sizeof(double));
@@ -316,7 +342,7 @@ static void finish(solve_server* S, Solve* s) {
 }
 
 static void server_loop(solve_server* S) {
-    hipSetDevice(S->device);
+    (void)hipSetDevice(S->device);
     std::vector<Solve*> run;
     while (true) {
         std::vector<Solve*> admitted;
@@ -348,17 +374,24 @@ static void server_loop(solve_server* S) {
             S->cv.notify_all();
             continue;
         }
-        int64_t chunk = kChunk;
-        for (Solve* s : run) chunk = std::min(chunk, s->n_steps - s->steps);
+        std::map<int, std::vector<Solve*>> groups;
+        for (Solve* s : run) groups[s->mesh.PP].push_back(s);
+        const std::map<int, int64_t> plan = round_plan(groups);
         const double t0 = now_s();
         int rc = DG_OK;
-        for (int64_t n = 0; n < chunk && rc == DG_OK; ++n) rc = step_all(S, run);
-        hipStreamSynchronize(S->st);
+        int64_t steps_done = 0;
+        for (auto& g : groups) {
+            hipStream_t gst = S->gst[g.first];
+            const int64_t n_g = plan.at(g.first);
+            for (int64_t n = 0; n < n_g && rc == DG_OK; ++n) rc = step_group(S, g.first, g.second, gst);
+            steps_done = std::max(steps_done, n_g);
+        }
+        for (auto& g : groups) (void)hipStreamSynchronize(S->gst[g.first]);
         const double t1 = now_s();
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->busy += t1 - t0;
-            S->batches += chunk;
+            S->batches += steps_done;
         }
         std::vector<Solve*> keep;
         for (Solve* s : run) {
@@ -415,8 +448,16 @@ int solve_server_create(void* arena, size_t arena_bytes, int32_t max_slots, solv
         delete S;
         return set_error(DG_EHIP, "stream creation failed");
     }
+    for (int pp = DG_MIN_ORDER + 1; pp <= kMaxPP; ++pp)
+        if (hipStreamCreateWithFlags(&S->gst[pp], hipStreamNonBlocking) != hipSuccess) {
+            for (int q = DG_MIN_ORDER + 1; q < pp; ++q) (void)hipStreamDestroy(S->gst[q]);
+            (void)hipStreamDestroy(S->st);
+            delete S;
+            return set_error(DG_EHIP, "stream creation failed");
+        }
     if (hipHostMalloc((void**)&S->pinned, kHist * kDiagDoubles * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        hipStreamDestroy(S->st);
+        (void)hipStreamDestroy(S->st);
+        for (int pp = DG_MIN_ORDER + 1; pp <= kMaxPP; ++pp) (void)hipStreamDestroy(S->gst[pp]);
         delete S;
         return set_error(DG_EHIP, "pinned buffer allocation failed");
     }
@@ -514,9 +555,13 @@ void solve_server_free(solve_server* S) {
     }
     S->cv.notify_all();
     if (S->th.joinable()) S->th.join();
-    hipStreamSynchronize(S->st);
-    hipStreamDestroy(S->st);
-    hipHostFree(S->pinned);
+    (void)hipStreamSynchronize(S->st);
+    (void)hipStreamDestroy(S->st);
+    for (int pp = DG_MIN_ORDER + 1; pp <= kMaxPP; ++pp) {
+        (void)hipStreamSynchronize(S->gst[pp]);
+        (void)hipStreamDestroy(S->gst[pp]);
+    }
+    (void)hipHostFree(S->pinned);
     delete S;
 }
 
