@@ -51,6 +51,17 @@ __device__ __forceinline__ int neighbour(int e, int N, int f) {
     return ex + N * (ey + N * ez);
 }
 
+// The neighbour across face f of element e at coordinates (cx, cy, cz)
+// (uniform across the block), without an integer division per thread.
+__device__ __forceinline__ int neighbour_at(int e, int N, int cx, int cy, int cz, int f) {
+    const int d = f >> 1;
+    const int cd = d == 0 ? cx : (d == 1 ? cy : cz);
+    const int stride = d == 0 ? 1 : (d == 1 ? N : N * N);
+    const int up = (cd + 1 == N) ? 1 - N : 1;
+    const int down = (cd == 0) ? N - 1 : -1;
+    return e + ((f & 1) ? up : down) * stride;
+}
+
 // node of the line through face-node (a, b) of a face normal to d, at position m
 template <int PP>
 __device__ __forceinline__ int line_node(int d, int a, int b, int m) {
@@ -59,9 +70,40 @@ __device__ __forceinline__ int line_node(int d, int a, int b, int m) {
 
 // --------------------------------------------------------------- physics
 
+// 1/x for x > 0 normal: hardware estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - x r), each doubling the correct bits
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// sqrt(x) for x > 0 normal: hardware 1/sqrt estimate y, then Goldschmidt's
+// coupled iteration on g ~ sqrt(x), h ~ 1/(2 sqrt(x)) and a final residual
+// correction g + h (x - g^2)
+__device__ __forceinline__ double sqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
+// value of the axis-d entry of a triple, for a runtime axis
+__device__ __forceinline__ double pick3(int d, double x0, double x1, double x2) {
+    return d == 0 ? x0 : (d == 1 ? x1 : x2);
+}
+
 // w = (u, v, w, T) with T = p / rho
 __device__ __forceinline__ void gradient_vars(const double q[5], double gm1, double w[4]) {
-    const double ir = 1.0 / q[0];
+    const double ir = recip(q[0]);
     w[0] = q[1] * ir;
     w[1] = q[2] * ir;
     w[2] = q[3] * ir;
@@ -69,46 +111,27 @@ __device__ __forceinline__ void gradient_vars(const double q[5], double gm1, dou
     w[3] = p * ir;
 }
 
-__device__ __forceinline__ double pressure(const double q[5], double gm1) {
-    const double ir = 1.0 / q[0];
-    return gm1 * (q[4] - 0.5 * ir * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
-}
-
-// inviscid flux along D (App. A), p_ref removed from the momentum rows
-template <int D>
-__device__ __forceinline__ void flux_inviscid(const double q[5], double gm1, double p_ref, double F[5]) {
-    const double ir = 1.0 / q[0];
-    const double vd = q[1 + D] * ir;
-    const double p = pressure(q, gm1);
-    F[0] = q[1 + D];
-    F[1] = q[1] * vd;
-    F[2] = q[2] * vd;
-    F[3] = q[3] * vd;
-    F[1 + D] += p - p_ref;
-    F[4] = (q[4] + p) * vd;
-}
-
 // Roe flux along +D, qL on the lower side (Roe 1981), no entropy fix
 template <int D>
 __device__ void flux_roe(const double qL[5], const double qR[5], const Phys& ph, double F[5]) {
     const double gm1 = ph.gm1;
     const double rL = qL[0], rR = qR[0];
-    const double iL = 1.0 / rL, iR = 1.0 / rR;
+    const double iL = recip(rL), iR = recip(rR);
     double vL[3], vR[3];
     for (int a = 0; a < 3; ++a) { vL[a] = qL[1 + a] * iL; vR[a] = qR[1 + a] * iR; }
     const double pL = gm1 * (qL[4] - 0.5 * rL * (vL[0] * vL[0] + vL[1] * vL[1] + vL[2] * vL[2]));
     const double pR = gm1 * (qR[4] - 0.5 * rR * (vR[0] * vR[0] + vR[1] * vR[1] + vR[2] * vR[2]));
     const double HL = (qL[4] + pL) * iL, HR = (qR[4] + pR) * iR;
-    const double sL = sqrt(rL), sR = sqrt(rR);
+    const double sL = sqrt_pos(rL), sR = sqrt_pos(rR);
     const double rt = sL * sR;
-    const double isum = 1.0 / (sL + sR);
+    const double isum = recip(sL + sR);
     double vt[3];
     for (int a = 0; a < 3; ++a) vt[a] = (sL * vL[a] + sR * vR[a]) * isum;
     const double Ht = (sL * HL + sR * HR) * isum;
     const double v2 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
-    const double ct = sqrt(gm1 * (Ht - 0.5 * v2));
+    const double ct = sqrt_pos(gm1 * (Ht - 0.5 * v2));
     const double vn = vt[D];
-    const double ic2 = 1.0 / (ct * ct);
+    const double ic2 = recip(ct * ct);
     const double dr = rR - rL, dp = pR - pL;
     double dv[3];
     for (int a = 0; a < 3; ++a) dv[a] = vR[a] - vL[a];
@@ -148,12 +171,12 @@ __device__ void flux_roe(const double qL[5], const double qR[5], const Phys& ph,
     for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * diss[v];
 }
 
-// One-sided viscous flux along D (App. A): momentum rows tau_{aD} and the
-// energy row sum_a v_a tau_{aD} + kappa dT/dx_D.  g[j][c] = d_j w_c.
-template <int D>
-__device__ __forceinline__ void flux_viscous(double rho, const double v[3], const double g[3][4],
-                                             const Phys& ph, double Fv[4]) {
-    double mu = ph.mu, kappa = ph.kappa;
+// Effective viscosity and conductivity: mu, kappa plus, with the Smagorinsky
+// closure, mu_t = rho (Cs Delta)^2 sqrt(2 S:S) and mu_t gamma/((gamma-1) Pr_t).
+__device__ __forceinline__ void effective_visc(double rho, const double g[3][4], const Phys& ph, double& mu,
+                                               double& kappa) {
+    mu = ph.mu;
+    kappa = ph.kappa;
     if (ph.les) {
         double SS = 0.0;
         for (int a = 0; a < 3; ++a)
@@ -165,6 +188,15 @@ __device__ __forceinline__ void flux_viscous(double rho, const double v[3], cons
         mu += mut;
         kappa += mut * ph.kt;
     }
+}
+
+// One-sided viscous flux along D (App. A): momentum rows tau_{aD} and the
+// energy row sum_a v_a tau_{aD} + kappa dT/dx_D.  g[j][c] = d_j w_c.
+template <int D>
+__device__ __forceinline__ void flux_viscous(double rho, const double v[3], const double g[3][4],
+                                             const Phys& ph, double Fv[4]) {
+    double mu, kappa;
+    effective_visc(rho, g, ph, mu, kappa);
     const double div = g[0][0] + g[1][1] + g[2][2];
     double e = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -176,33 +208,102 @@ __device__ __forceinline__ void flux_viscous(double rho, const double v[3], cons
     Fv[3] = e + kappa * g[D][3];
 }
 
-template <int D>
-__device__ __forceinline__ void flux_net(const double q[5], const double g[3][4], const Phys& ph, double G[5]) {
-    flux_inviscid<D>(q, ph.gm1, ph.p_ref, G);
+// Node quantities that the three directions of the volume flux share:
+// velocity, p - p_ref (momentum rows), rho E + p (energy row), and the
+// effective mu, kappa and (2/3) mu div v.
+struct NodeState {
+    double v[3], pt, pe, mu, kappa, lam;
+};
+
+__device__ __forceinline__ void node_state(const double q[5], const double g[3][4], const Phys& ph, NodeState& n) {
+    const double ir = recip(q[0]);
+    n.v[0] = q[1] * ir;
+    n.v[1] = q[2] * ir;
+    n.v[2] = q[3] * ir;
+    const double p = ph.gm1 * (q[4] - 0.5 * (q[1] * n.v[0] + q[2] * n.v[1] + q[3] * n.v[2]));
+    n.pt = p - ph.p_ref;
+    n.pe = q[4] + p;
     if (ph.viscous) {
-        const double ir = 1.0 / q[0];
-        const double v[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
-        double Fv[4];
-        flux_viscous<D>(q[0], v, g, ph, Fv);
-        G[1] -= Fv[0];
-        G[2] -= Fv[1];
-        G[3] -= Fv[2];
-        G[4] -= Fv[3];
+        effective_visc(q[0], g, ph, n.mu, n.kappa);
+        n.lam = (2.0 / 3.0) * n.mu * (g[0][0] + g[1][1] + g[2][2]);
     }
 }
 
-__device__ __forceinline__ void flux_viscous_dir(int d, double rho, const double v[3], const double g[3][4],
-                                                 const Phys& ph, double Fv[4]) {
-    if (d == 0) flux_viscous<0>(rho, v, g, ph, Fv);
-    else if (d == 1) flux_viscous<1>(rho, v, g, ph, Fv);
-    else flux_viscous<2>(rho, v, g, ph, Fv);
+// net volume flux along D: inviscid (App. A, p_ref removed from the momentum
+// rows) minus viscous
+template <int D>
+__device__ __forceinline__ void flux_net(const double q[5], const double g[3][4], const NodeState& n,
+                                         const Phys& ph, double G[5]) {
+    const double vd = n.v[D];
+    G[0] = q[1 + D];
+    G[1] = q[1] * vd;
+    G[2] = q[2] * vd;
+    G[3] = q[3] * vd;
+    G[1 + D] += n.pt;
+    G[4] = n.pe * vd;
+    if (ph.viscous) {
+        double e = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double tau = n.mu * (g[a][D] + g[D][a]);
+            if (a == D) tau -= n.lam;
+            G[1 + a] -= tau;
+            e += n.v[a] * tau;
+        }
+        G[4] -= e + n.kappa * g[D][3];
+    }
 }
 
-__device__ __forceinline__ void flux_roe_dir(int d, const double qL[5], const double qR[5], const Phys& ph,
+// One-sided viscous flux across a face normal to axis d: flux_viscous<0> of
+// the velocity and gradient with axes relabelled cyclically so that d comes
+// first (both the derivative axis and the velocity component), relabelled
+// back; one code path for the three orientations.
+__device__ __forceinline__ void flux_viscous_rot(int d, double rho, const double v[3], const double g[3][4],
+                                                 const Phys& ph, double Fv[4]) {
+    // entry (r, c) of the relabelled gradient is entry ((r + d) mod 3, (c + d) mod 3)
+    double vr[3], gr[3][4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        vr[r] = pick3(d, v[r], v[(r + 1) % 3], v[(r + 2) % 3]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            gr[r][c] = pick3(d, g[r][c], g[(r + 1) % 3][(c + 1) % 3], g[(r + 2) % 3][(c + 2) % 3]);
+        gr[r][3] = pick3(d, g[r][3], g[(r + 1) % 3][3], g[(r + 2) % 3][3]);
+    }
+    double Fr[4];
+    flux_viscous<0>(rho, vr, gr, ph, Fr);
+    Fv[0] = pick3(d, Fr[0], Fr[2], Fr[1]);
+    Fv[1] = pick3(d, Fr[1], Fr[0], Fr[2]);
+    Fv[2] = pick3(d, Fr[2], Fr[1], Fr[0]);
+    Fv[3] = Fr[3];
+}
+
+// Roe flux across a face normal to axis d (qL on the lower side): the
+// x-direction flux of the states with their axes relabelled cyclically so
+// that d comes first (rotated momentum r is original momentum (r + d) mod 3),
+// relabelled back.  One code path serves the three orientations, so the
+// lanes of a wavefront whose face nodes straddle faces of different
+// orientation run the flux once instead of once per orientation under masks.
+__device__ __forceinline__ void flux_roe_rot(int d, const double qL[5], const double qR[5], const Phys& ph,
                                              double F[5]) {
-    if (d == 0) flux_roe<0>(qL, qR, ph, F);
-    else if (d == 1) flux_roe<1>(qL, qR, ph, F);
-    else flux_roe<2>(qL, qR, ph, F);
+    double a[5], b[5];
+    a[0] = qL[0];
+    b[0] = qR[0];
+    a[4] = qL[4];
+    b[4] = qR[4];
+    a[1] = pick3(d, qL[1], qL[2], qL[3]);
+    a[2] = pick3(d, qL[2], qL[3], qL[1]);
+    a[3] = pick3(d, qL[3], qL[1], qL[2]);
+    b[1] = pick3(d, qR[1], qR[2], qR[3]);
+    b[2] = pick3(d, qR[2], qR[3], qR[1]);
+    b[3] = pick3(d, qR[3], qR[1], qR[2]);
+    double G[5];
+    flux_roe<0>(a, b, ph, G);
+    F[0] = G[0];
+    F[4] = G[4];
+    F[1] = pick3(d, G[1], G[3], G[2]);
+    F[2] = pick3(d, G[2], G[1], G[3]);
+    F[3] = pick3(d, G[3], G[2], G[1]);
 }
 
 // ----------------------------------------------------- element-local pieces
@@ -352,6 +453,7 @@ __global__ void __launch_bounds__(Shape<PP>::NT) k_grad(DescList dl) {
     const SolveDesc& D = *dl.d[si];
     const Phys ph = D.ph;
     const int e = b - dl.blk[si];
+    const int ecx = e % D.N, ecy = (e / D.N) % D.N, ecz = e / (D.N * D.N);
     const int E = D.E;
     const int t = threadIdx.x;
     const BasisTab& B = c_basis[PP - 2];
@@ -374,7 +476,7 @@ __global__ void __launch_bounds__(Shape<PP>::NT) k_grad(DescList dl) {
             const int f = tau / NF, fn = tau - f * NF;
             double qi[5], qo[5];
             face_interp<PP, 5>(sh, B, f, fn, qi);
-            const int nb = neighbour(e, D.N, f);
+            const int nb = neighbour_at(e, D.N, ecx, ecy, ecz, f);
             const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
 #pragma unroll
             for (int v = 0; v < 5; ++v) qo[v] = tr[v * NF];
@@ -425,7 +527,7 @@ __global__ void __launch_bounds__(Shape<PP>::NT) k_grad(DescList dl) {
                 for (int c = 0; c < 4; ++c) gf[d][c] = gi[d * 4 + c];
             const double v[3] = {fq[r][1], fq[r][2], fq[r][3]};
             double Fv[4];
-            flux_viscous_dir(f >> 1, fq[r][0], v, gf, ph, Fv);
+            flux_viscous_rot(f >> 1, fq[r][0], v, gf, ph, Fv);
             double* o = D.fv + (size_t)(e * 6 + f) * 4 * NF + fn;
 #pragma unroll
             for (int c = 0; c < 4; ++c) o[c * NF] = Fv[c];
@@ -448,6 +550,7 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     const SolveDesc& D = *dl.d[si];
     const Phys ph = D.ph;
     const int e = b - dl.blk[si];
+    const int ecx = e % D.N, ecy = (e / D.N) % D.N, ecz = e / (D.N * D.N);
     const int E = D.E;
     const int t = threadIdx.x;
     const BasisTab& B = c_basis[PP - 2];
@@ -472,13 +575,20 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
             const int d = f >> 1;
             double qi[5], qo[5];
             face_interp<PP, 5>(sh, B, f, fn, qi);
-            const int nb = neighbour(e, D.N, f);
+            const int nb = neighbour_at(e, D.N, ecx, ecy, ecz, f);
             const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
 #pragma unroll
             for (int v = 0; v < 5; ++v) qo[v] = tr[v * NF];
+            // the lower-side state is the neighbour's on a lower face
+            const bool up = f & 1;
+            double qL[5], qR[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                qL[v] = up ? qi[v] : qo[v];
+                qR[v] = up ? qo[v] : qi[v];
+            }
             double F[5];
-            if (f & 1) flux_roe_dir(d, qi, qo, ph, F);
-            else flux_roe_dir(d, qo, qi, ph, F);
+            flux_roe_rot(d, qL, qR, ph, F);
             if (ph.viscous) {
                 const double* fi = D.fv + (size_t)(e * 6 + f) * 4 * NF + fn;
                 const double* fo = D.fv + (size_t)(nb * 6 + (f ^ 1)) * 4 * NF + fn;
@@ -517,15 +627,17 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
             for (int c = 0; c < 4; ++c) g[d][c] = 0.0;
     }
 
+    NodeState ns;
+    if (t < NP) node_state(qn, g, ph, ns);
     double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         __syncthreads();
         if (t < NP) {
             double G[5];
-            if (d == 0) flux_net<0>(qn, g, ph, G);
-            else if (d == 1) flux_net<1>(qn, g, ph, G);
-            else flux_net<2>(qn, g, ph, G);
+            if (d == 0) flux_net<0>(qn, g, ns, ph, G);
+            else if (d == 1) flux_net<1>(qn, g, ns, ph, G);
+            else flux_net<2>(qn, g, ns, ph, G);
 #pragma unroll
             for (int v = 0; v < 5; ++v) sh[v * NP + t] = G[v];
         }

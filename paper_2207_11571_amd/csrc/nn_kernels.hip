@@ -1,7 +1,7 @@
 // Forcing network kernels for gfx950: bf16 MFMA (v_mfma_f32_16x16x32_bf16)
 // with float32 accumulation.
 //
-// Inference (Sec. 2.2, Eq. (4)): one block of eight wavefronts takes 16
+// Inference (Sec. 2.2, Eq. (4)): one block of sixteen wavefronts takes 16
 // elements; their states are gathered from the DG layout q[v][e][n],
 // normalised and rounded to bf16 in LDS; every layer is a 16 x N x K product
 // of the LDS-resident activations with the bf16 weights read from L2, with
@@ -23,7 +23,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRows = 16;      // rows (elements / samples) per block
 constexpr int kThreads = 256;     // weight-gradient blocks: four wavefronts, one tile each
-constexpr int kRowWaves = 8;      // row-block kernels: eight wavefronts share the column tiles
+constexpr int kRowWaves = 16;     // row-block kernels: sixteen wavefronts share the column tiles
 constexpr int kRowThreads = 64 * kRowWaves;
 constexpr int kLdPad = 8;      // LDS row padding (bf16 elements)
 
@@ -43,10 +43,11 @@ __device__ __forceinline__ float act_fwd(float z, int act) { return act == 0 ? t
 __device__ __forceinline__ float act_bwd(float h, int act) { return act == 0 ? 1.0f - h * h : (h > 0.0f ? 1.0f : 0.0f); }
 
 // C[16][Np] = A[16][Kp] W^T with W [Np][Kp] row-major bf16 in global memory.
-// Wave w computes the 16-column tiles w, w + 4, ...; epi(m, n, value) per output.
-// For the common widths the K loop is unrolled and the weight fragments of
-// the next tile are loaded while the current tile's MFMAs run (the weights
-// come from L2; their latency, not the matrix cores, bounds this product).
+// Wave w computes the 16-column tiles w, w + kRowWaves, ...; epi(m, n, value)
+// per output.  For the common widths the K loop is unrolled so that all of a
+// tile's weight fragments are in flight at once: the weights come from L2 and
+// their latency, not the matrix cores, bounds this product, so sixteen
+// wavefronts (one or two tiles each) beat fewer wavefronts with prefetching.
 template <int KP, class Epi>
 __device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, int ldA,
                                                const uint16_t* __restrict__ W, int Np, int wave, int lane, Epi& epi) {
@@ -54,23 +55,11 @@ __device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, 
     const int kq = 8 * (lane >> 4);
     const int r = lane & 15;
     const uint16_t* arow = sA + r * ldA + kq;
-    const int ntiles = Np / 16;
-    int tile = wave;
-    if (tile >= ntiles) return;
-    bf16x8 b[KS];
-    {
+    for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
         const uint16_t* wrow = W + (size_t)(tile * 16 + r) * KP + kq;
+        bf16x8 b[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s) b[s] = *(const bf16x8*)(wrow + 32 * s);
-    }
-    for (; tile < ntiles; tile += kRowWaves) {
-        const int next = tile + kRowWaves;
-        bf16x8 bn[KS];
-        if (next < ntiles) {
-            const uint16_t* wrow = W + (size_t)(next * 16 + r) * KP + kq;
-#pragma unroll
-            for (int s = 0; s < KS; ++s) bn[s] = *(const bf16x8*)(wrow + 32 * s);
-        }
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
@@ -80,10 +69,6 @@ __device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, 
         const int n = tile * 16 + r;
 #pragma unroll
         for (int i = 0; i < 4; ++i) epi(4 * (lane >> 4) + i, n, acc[i]);
-        if (next < ntiles) {
-#pragma unroll
-            for (int s = 0; s < KS; ++s) b[s] = bn[s];
-        }
     }
 }
 
