@@ -10,14 +10,29 @@ mapped back with s_v = mask[v] (sigma_out[v] yhat_v + mu_out[v]).  The paper
 feeds only the momentum and forces only the momentum (mask (0,1,1,1,0)); the
 workload measured here feeds and forces all five variables.
 
+The network may also see and force a subset of the variables (in_vars,
+out_vars): its input row is then the selected variables' nodal values only,
+and the forcing of the other variables is zero.  The paper's network reads
+and forces the three momenta (Sec. 2.2).
+
 Training target (Eq. (5), with the low-order state equal to the filtered
 high-order one, as Algorithm 1 sets it before each low-order step):
     x = G q_HO,    y = G p_HO(q_HO) - p_LO(G q_HO).
+
+Algorithm 1's own target is the discrete increment over one low-order step
+dt_n: with q_NN^n = G q_HO^n advanced one uncorrected low-order step to
+q_NN^{n+1}, and q_HO advanced over the same interval in m high-order steps,
+    s_n = (G q_HO^{n+1} - q_NN^{n+1}) / dt_n,   paired with x = q_NN^n;
+the low-order evolution then corrects after each uncorrected step,
+q^{n+1} <- q^{n+1} + dt_n s_n, with s_n evaluated on q^n.
 """
 import numpy as np
 
-from . import dg, mlp, projection
+from . import dg, mlp, projection, rk
 from .basis import Basis
+
+ALL_VARS = (0, 1, 2, 3, 4)
+MOMENTUM = (1, 2, 3)
 
 
 class Normalisation:
@@ -45,24 +60,28 @@ def rows_to_field(Y, nv, n_p):
     return np.transpose(Y.reshape(E, nv, n_p), (1, 0, 2))
 
 
-def network_forcing(q_flat, params, norm, act="tanh"):
-    """s(q) for every element; q_flat[5][E][n_p] -> s[5][E][n_p]."""
+def network_forcing(q_flat, params, norm, act="tanh", in_vars=ALL_VARS, out_vars=ALL_VARS):
+    """s(q) for every element; q_flat[5][E][n_p] -> s[5][E][n_p].  The
+    network reads the variables in_vars and forces the variables out_vars."""
     nv, E, n_p = q_flat.shape
-    X = element_rows(q_flat)
-    scale_in = np.repeat(norm.sigma_in, n_p)
-    shift_in = np.repeat(norm.mu_in, n_p)
-    yhat = mlp.forward(params, (X - shift_in) / scale_in, act)[-1]
-    s = yhat * np.repeat(norm.sigma_out, n_p) + np.repeat(norm.mu_out, n_p)
-    s = s * np.repeat(norm.mask, n_p)
-    return rows_to_field(s, nv, n_p)
+    iv, ov = list(in_vars), list(out_vars)
+    X = element_rows(q_flat[iv])
+    xhat = (X - np.repeat(norm.mu_in[iv], n_p)) / np.repeat(norm.sigma_in[iv], n_p)
+    yhat = mlp.forward(params, xhat, act)[-1]
+    s_sel = yhat * np.repeat(norm.sigma_out[ov], n_p) + np.repeat(norm.mu_out[ov], n_p)
+    s_sel = s_sel * np.repeat(norm.mask[ov], n_p)
+    s = np.zeros_like(np.asarray(q_flat, dtype=np.float64))
+    s[ov] = rows_to_field(s_sel, len(ov), n_p)
+    return s
 
 
-def corrected_rhs(q_blocks, prm, params=None, norm=None, act="tanh", basis=None):
+def corrected_rhs(q_blocks, prm, params=None, norm=None, act="tanh", basis=None, in_vars=ALL_VARS,
+                  out_vars=ALL_VARS):
     """Right-hand side of Eq. (4): p_LO(q) + s(q) (s omitted when params is None)."""
     R = dg.residual(q_blocks, prm, basis)
     if params is None:
         return R
-    s = network_forcing(dg.to_flat(q_blocks), params, norm, act)
+    s = network_forcing(dg.to_flat(q_blocks), params, norm, act, in_vars, out_vars)
     return R + dg.to_blocks(s, prm.N, prm.P)
 
 
@@ -90,3 +109,30 @@ def normalisation_from_pairs(X, Y, nv=5):
     mi, si = stats(np.asarray(X, dtype=np.float64))
     mo, so = stats(np.asarray(Y, dtype=np.float64))
     return Normalisation(mi, si, mo, so)
+
+
+def increment_target(q_hi, prm_hi, prm_lo, dt_lo, m_sub):
+    """One low-order step of Algorithm 1's high-order evolution.
+
+    Sets the low-order state to the filtered high-order one, advances it one
+    uncorrected low-order step of dt_lo, advances the high-order state over
+    the same interval in m_sub steps of dt_lo / m_sub, filters it, and forms
+    the discrete forcing s = (G q_HO^{n+1} - q_NN^{n+1}) / dt_lo.
+    Returns (x rows = q_NN^n, y rows = s, q_HO^{n+1}); rows [E][5 n_p_lo]."""
+    P_hi, P_lo = prm_hi.P, prm_lo.P
+    b_hi, b_lo = Basis(P_hi), Basis(P_lo)
+    q_nn = projection.project(q_hi, P_hi, P_lo)
+    q_nn1 = rk.rk3_step(q_nn, dt_lo, lambda q, t: dg.residual(q, prm_lo, b_lo))
+    q_hi1 = rk.integrate(q_hi, dt_lo / m_sub, m_sub, lambda q, t: dg.residual(q, prm_hi, b_hi))
+    s = (projection.project(q_hi1, P_hi, P_lo) - q_nn1) / dt_lo
+    return element_rows(dg.to_flat(q_nn)), element_rows(dg.to_flat(s)), q_hi1
+
+
+def post_corrected_step(q_blocks, prm, dt, params, norm, act="relu", in_vars=MOMENTUM, out_vars=MOMENTUM,
+                        basis=None):
+    """Algorithm 1's low-order step: the uncorrected step q^n -> q^{n+1}, then
+    q^{n+1} + dt s(q^n)."""
+    basis = basis or Basis(prm.P)
+    s = network_forcing(dg.to_flat(q_blocks), params, norm, act, in_vars, out_vars)
+    q1 = rk.rk3_step(q_blocks, dt, lambda q, t: dg.residual(q, prm, basis))
+    return q1 + dt * dg.to_blocks(s, prm.N, prm.P)
