@@ -105,6 +105,15 @@ typedef struct nn_model nn_model;
 int dg_rk_step(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps,
                const nn_model* forcing, void* ws, size_t ws_bytes, void* stream);
 
+/* The low-order evolution of Algorithm 1: each of the n_steps steps is the
+ * uncorrected Runge-Kutta step q^n -> q^{n+1} followed by the correction
+ * q^{n+1} += dt s(q^n), s evaluated on the state at the start of the step
+ * (forcing == NULL gives plain uncorrected steps).  The correction is added
+ * in the last stage's update, so the face traces that the next step reads
+ * already include it.  Arguments and errors as dg_rk_step. */
+int dg_rk_step_post(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps,
+                    const nn_model* forcing, void* ws, size_t ws_bytes, void* stream);
+
 /* Measurement twin of dg_rk_step: the same launches, each bracketed by a HIP
  * event pair on `stream`; out_ms (host, double[4]) receives the mean duration
  * in milliseconds of one launch of each stage kernel: [0] face traces,
@@ -144,6 +153,19 @@ size_t dg_forcing_target_ws(const dg_mesh* hi, const dg_mesh* lo);
 int dg_forcing_target(const dg_mesh* hi, const dg_mesh* lo, const double* q_hi,
                       float* x_out, float* y_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Training pairs of Algorithm 1 (the discrete increment over one low-order
+ * step) for one low-order step of length dt_lo: with q_NN = G q_hi advanced
+ * one uncorrected low-order Runge-Kutta step to q_NN', and q_hi advanced IN
+ * PLACE over the same interval by m_sub >= 1 steps of dt_lo / m_sub (k_hi is
+ * its Runge-Kutta register, contents ignored on entry),
+ *   x = q_NN,   y = (G q_hi' - q_NN') / dt_lo,
+ * written as float rows x_out[E][5 n_p_lo], y_out[E][5 n_p_lo].  Calling it
+ * once per low-order step of a training window is the high-order evolution
+ * of Algorithm 1.  ws must hold dg_increment_target_ws() bytes. */
+size_t dg_increment_target_ws(const dg_mesh* hi, const dg_mesh* lo);
+int dg_increment_target(const dg_mesh* hi, const dg_mesh* lo, double* q_hi, double* k_hi, double dt_lo,
+                        int32_t m_sub, float* x_out, float* y_out, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------- forcing network */
 
 /* The fully connected forcing network of Sec. 2.2, one network shared by all
@@ -162,6 +184,19 @@ int nn_query(const int32_t* dims, int32_t n_layers, int64_t* n_params, int64_t* 
 int nn_init(const int32_t* dims, int32_t n_layers, int32_t activation,
             float* params, uint16_t* w_bf16, float* grad, float* adam_m, float* adam_v,
             const double* norm, const uint8_t* mask, void* stream, nn_model** out);
+/* nn_init for a network that reads only the variables v with in_vars[v] != 0
+ * and forces only those with out_vars[v] != 0 (host arrays of 5; NULL selects
+ * all five), as the paper's network reads and forces the three momenta
+ * (Sec. 2.2).  dims[0] = (variables read) x n_p and dims[n_layers] =
+ * (variables forced) x n_p, the same n_p; input column j n_p + n is node n of
+ * the j-th variable read, output columns likewise, and the forcing of the
+ * other variables is zero.  norm and mask keep their five-variable layout.
+ * nn_init is nn_init_io with every variable read and forced.  DG_EINVAL when
+ * no variable is selected or the sizes do not fit the selection. */
+int nn_init_io(const int32_t* dims, int32_t n_layers, int32_t activation,
+               const uint8_t* in_vars, const uint8_t* out_vars,
+               float* params, uint16_t* w_bf16, float* grad, float* adam_m, float* adam_v,
+               const double* norm, const uint8_t* mask, void* stream, nn_model** out);
 /* Re-derives the bfloat16 copies after the caller rewrote params. */
 int nn_refresh(nn_model* model, void* stream);
 /* Replaces the normalisation (host array of 20 doubles) and the mask. */
@@ -179,8 +214,10 @@ size_t nn_train_ws(const nn_model* model, int32_t batch);
 
 /* One Adam step (Kingma-Ba, bias-corrected, beta1 0.9, beta2 0.999, eps 1e-7)
  * of the MSE loss mean((yhat - (y - mu_out)/sigma_out)^2) (Sec. 2.1, Table 1:
- * mean square error) on a batch of training pairs: x[.][n_in], y[.][n_out]
- * are float32 rows in physical units (device); the batch is rows
+ * mean square error) on a batch of training pairs: x, y are float32 rows of
+ * all five variables, [.][5 n_p] variable-major, in physical units (device),
+ * from which the network takes the variables it reads and forces; the loss
+ * runs over the forced ones.  The batch is rows
  * idx[0..batch) of them (device int32, each < the caller's row count), or
  * rows 0..batch-1 when idx is NULL.  Forward and backward run on bfloat16
  * matrix cores with float32 accumulation; the float32 master weights, grad,

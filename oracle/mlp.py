@@ -47,22 +47,32 @@ def activation_grad_from_output(h, kind):
     raise ValueError(kind)
 
 
-def forward(params, x, act="tanh"):
+def forward(params, x, act="tanh", quantise=False):
     """All layer outputs [h_0 = x, h_1, ..., yhat] for a batch x[B, n_in].
-    ``params`` is a list of (W[out, in], b[out])."""
+    ``params`` is a list of (W[out, in], b[out]).  quantise=True stores the
+    input and every hidden layer's output as bfloat16 (the device network's
+    precision for the activations between layers); the arithmetic stays float64."""
     h = np.asarray(x, dtype=np.float64)
+    if quantise:
+        h = bf16_round(h)
     outs = [h]
     L = len(params)
     for l, (W, b) in enumerate(params):
         z = h @ np.asarray(W, dtype=np.float64).T + np.asarray(b, dtype=np.float64)
-        h = z if l == L - 1 else activation(z, act)
+        if l == L - 1:
+            h = z
+        else:
+            h = activation(z, act)
+            if quantise:
+                h = bf16_round(h)
         outs.append(h)
     return outs
 
 
-def mse_loss_and_grads(params, x, y, act="tanh"):
-    """Loss and its gradients [(dW, db), ...] for one batch."""
-    outs = forward(params, x, act)
+def mse_loss_and_grads(params, x, y, act="tanh", quantise=False):
+    """Loss and its gradients [(dW, db), ...] for one batch (quantise: as in
+    ``forward``; the backward pass is float64 either way)."""
+    outs = forward(params, x, act, quantise)
     yhat = outs[-1]
     B, n_out = yhat.shape
     diff = yhat - y

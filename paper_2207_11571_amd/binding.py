@@ -59,6 +59,7 @@ SIGNATURES = {
     "dg_init_tgv": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "dg_rk_step": (ctypes.c_int, [_vp, _vp, _vp, _d, _i32, _vp, _vp, _sz, _vp]),
+    "dg_rk_step_post": (ctypes.c_int, [_vp, _vp, _vp, _d, _i32, _vp, _vp, _sz, _vp]),
     "dg_profile_steps": (ctypes.c_int, [_vp, _vp, _vp, _d, _i32, _vp, _vp, _sz, _vp, ctypes.POINTER(_d)]),
     "dg_diagnostics": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "dg_stable_dt": (ctypes.c_int, [_vp, _vp, _d, ctypes.POINTER(_d), _vp, _sz, _vp]),
@@ -66,9 +67,14 @@ SIGNATURES = {
     "dg_project": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "dg_forcing_target_ws": (_sz, [_vp, _vp]),
     "dg_forcing_target": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "dg_increment_target_ws": (_sz, [_vp, _vp]),
+    "dg_increment_target": (ctypes.c_int, [_vp, _vp, _vp, _vp, _d, _i32, _vp, _vp, _vp, _sz, _vp]),
     "nn_query": (ctypes.c_int, [ctypes.POINTER(_i32), _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "nn_init": (ctypes.c_int, [ctypes.POINTER(_i32), _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                                ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_uint8), _vp, ctypes.POINTER(_vp)]),
+    "nn_init_io": (ctypes.c_int, [ctypes.POINTER(_i32), _i32, _i32, ctypes.POINTER(ctypes.c_uint8),
+                                  ctypes.POINTER(ctypes.c_uint8), _vp, _vp, _vp, _vp, _vp,
+                                  ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_uint8), _vp, ctypes.POINTER(_vp)]),
     "nn_refresh": (ctypes.c_int, [_vp, _vp]),
     "nn_set_norm": (ctypes.c_int, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_uint8)]),
     "nn_free": (None, [_vp]),
@@ -184,6 +190,12 @@ def dg_rk_step(mesh, q, k, dt, n_steps, model=None, stream=None):
                            _stream(stream)))
 
 
+def dg_rk_step_post(mesh, q, k, dt, n_steps, model=None, stream=None):
+    check(lib().dg_rk_step_post(mesh.handle, _ptr(q, torch.float64, "q"), _ptr(k, torch.float64, "k"), float(dt),
+                                int(n_steps), model.handle if model is not None else None, _ptr(mesh.ws),
+                                mesh.ws_bytes, _stream(stream)))
+
+
 def dg_profile_steps(mesh, q, k, dt, n_steps, model=None, stream=None):
     out = (ctypes.c_double * 4)()
     check(lib().dg_profile_steps(mesh.handle, _ptr(q, torch.float64, "q"), _ptr(k, torch.float64, "k"), float(dt),
@@ -227,6 +239,17 @@ def dg_forcing_target(hi, lo, q_hi, x_out, y_out, ws=None, stream=None):
     return ws
 
 
+def dg_increment_target(hi, lo, q_hi, k_hi, dt_lo, m_sub, x_out, y_out, ws=None, stream=None):
+    need = lib().dg_increment_target_ws(hi.handle, lo.handle)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=q_hi.device)
+    check(lib().dg_increment_target(hi.handle, lo.handle, _ptr(q_hi, torch.float64, "q_hi"),
+                                    _ptr(k_hi, torch.float64, "k_hi"), float(dt_lo), int(m_sub),
+                                    _ptr(x_out, torch.float32, "x_out"), _ptr(y_out, torch.float32, "y_out"),
+                                    _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
 def nn_query(dims):
     arr = (ctypes.c_int32 * len(dims))(*dims)
     n_params, n_bf16 = ctypes.c_int64(), ctypes.c_int64()
@@ -258,7 +281,9 @@ class Model:
     gradient and Adam moments)."""
 
     def __init__(self, dims, flat_params, norm, mask=(1, 1, 1, 1, 1), activation="tanh", train=True, device="cuda",
-                 stream=None):
+                 stream=None, in_vars=None, out_vars=None):
+        """in_vars / out_vars: the variables (indices 0..4) the network reads and
+        forces; None = all five."""
         self.dims = list(dims)
         n_params, n_bf16 = nn_query(self.dims)
         self.params = torch.as_tensor(flat_params, dtype=torch.float32).to(device).contiguous()
@@ -272,8 +297,14 @@ class Model:
         nrm = (ctypes.c_double * 20)(*[float(x) for x in norm])
         msk = (ctypes.c_uint8 * 5)(*[1 if x else 0 for x in mask])
         h = ctypes.c_void_p()
-        check(lib().nn_init(arr, len(dims) - 1, 0 if activation == "tanh" else 1, _ptr(self.params), _ptr(self.wbf),
-                            _ptr(self.grad), _ptr(self.m), _ptr(self.v), nrm, msk, _stream(stream), ctypes.byref(h)))
+        def sel(vs):
+            return None if vs is None else (ctypes.c_uint8 * 5)(*[1 if v in vs else 0 for v in range(5)])
+
+        self.in_vars = tuple(range(5)) if in_vars is None else tuple(in_vars)
+        self.out_vars = tuple(range(5)) if out_vars is None else tuple(out_vars)
+        check(lib().nn_init_io(arr, len(dims) - 1, 0 if activation == "tanh" else 1, sel(in_vars), sel(out_vars),
+                               _ptr(self.params), _ptr(self.wbf), _ptr(self.grad), _ptr(self.m), _ptr(self.v), nrm,
+                               msk, _stream(stream), ctypes.byref(h)))
         self.handle = h
         self.train_ws = None
 

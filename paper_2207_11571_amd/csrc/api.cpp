@@ -233,32 +233,43 @@ int residual_impl(const Mesh& m, const double* q, double* dqdt, char* ws, hipStr
 const double kRkA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 const double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 
-int rk_impl(const Mesh& m, double* q, double* k, double dt, int n_steps, const nn_model* model, char* ws,
-            hipStream_t st) {
+int rk_impl(const Mesh& m, double* q, double* k, double dt, int n_steps, const nn_model* model, int post,
+            char* ws, hipStream_t st) {
     const WsLayout L = ws_layout(m);
-    SolveDesc d[2];
-    for (int p = 0; p < 2; ++p) {
+    const double* fbuf = model ? (const double*)(ws + L.forcing) : nullptr;
+    // d[par]: the stages; d[2 + par]: the last stage of a post-corrected step
+    SolveDesc d[4];
+    for (int p = 0; p < 4; ++p) {
+        const int par = p & 1;
         d[p] = make_desc(m, ws, L);
         d[p].q = q;
         d[p].k = k;
         d[p].dt = dt;
-        d[p].forcing = model ? (const double*)(ws + L.forcing) : nullptr;
-        d[p].qtr_in = (const double*)(ws + (p == 0 ? L.qtr0 : L.qtr1));
-        d[p].qtr_out = (double*)(ws + (p == 0 ? L.qtr1 : L.qtr0));
+        d[p].forcing = post ? nullptr : fbuf;
+        d[p].post = (post && p >= 2) ? fbuf : nullptr;
+        d[p].qtr_in = (const double*)(ws + (par == 0 ? L.qtr0 : L.qtr1));
+        d[p].qtr_out = (double*)(ws + (par == 0 ? L.qtr1 : L.qtr0));
     }
     SolveDesc* dd = (SolveDesc*)(ws + L.desc);
-    DG_HIP(launch_write_descs(d, 2, dd, st));
-    const DescList dl[2] = {single_list(dd, m.E), single_list(dd + 1, m.E)};
+    DG_HIP(launch_write_descs(d, 4, dd, st));
+    DescList dl[4];
+    for (int p = 0; p < 4; ++p) dl[p] = single_list(dd + p, m.E);
     DG_HIP(launch_traces(m.PP, dl[1], st));   // traces of q into qtr0
     int par = 0;
     for (int n = 0; n < n_steps; ++n) {
+        // post-step correction (Algorithm 1): s from the state at the start of the step
+        if (model && post) {
+            int rc = net_forcing_impl(model, m, q, (double*)(ws + L.forcing), /*accumulate=*/0, st);
+            if (rc != DG_OK) return rc;
+        }
         for (int s = 0; s < 3; ++s) {
-            if (m.ph.viscous) DG_HIP(launch_grad(m.PP, dl[par], st));
-            if (model) {
+            const DescList& l = dl[(post && model && s == 2 ? 2 : 0) + par];
+            if (m.ph.viscous) DG_HIP(launch_grad(m.PP, l, st));
+            if (model && !post) {
                 int rc = net_forcing_impl(model, m, q, (double*)(ws + L.forcing), /*accumulate=*/0, st);
                 if (rc != DG_OK) return rc;
             }
-            DG_HIP(launch_resid(m.PP, 1, dl[par], kRkA[s], kRkB[s], s == 0, st));
+            DG_HIP(launch_resid(m.PP, 1, l, kRkA[s], kRkB[s], s == 0, st));
             par ^= 1;
         }
     }
@@ -379,7 +390,21 @@ int dg_rk_step(const dg_mesh* m, double* q, double* k, double dt, int32_t n_step
     if ((rc = check_ws(m->m, ws, ws_bytes))) return rc;
     if (forcing && (rc = net_check_mesh(forcing, m->m))) return rc;
     if (n_steps == 0) return DG_OK;
-    return rk_impl(m->m, q, k, dt, n_steps, forcing, (char*)ws, (hipStream_t)stream);
+    return rk_impl(m->m, q, k, dt, n_steps, forcing, 0, (char*)ws, (hipStream_t)stream);
+}
+
+int dg_rk_step_post(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps, const nn_model* forcing,
+                    void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_mesh(m);
+    if (rc) return rc;
+    if (!q || !k || !aligned8(q) || !aligned8(k)) return set_error(DG_EINVAL, "bad state pointers");
+    if (q == k) return set_error(DG_EINVAL, "q and k alias");
+    if (!(dt > 0) || !std::isfinite(dt)) return set_error(DG_EINVAL, "dt must be positive and finite");
+    if (n_steps < 0) return set_error(DG_EINVAL, "negative step count");
+    if ((rc = check_ws(m->m, ws, ws_bytes))) return rc;
+    if (forcing && (rc = net_check_mesh(forcing, m->m))) return rc;
+    if (n_steps == 0) return DG_OK;
+    return rk_impl(m->m, q, k, dt, n_steps, forcing, 1, (char*)ws, (hipStream_t)stream);
 }
 
 int dg_profile_steps(const dg_mesh* mh, double* q, double* k, double dt, int32_t n_steps, const nn_model* model,
@@ -545,7 +570,48 @@ int dg_forcing_target(const dg_mesh* hi, const dg_mesh* lo, const double* q_hi, 
     if ((rc = project_impl(hi->m, lo->m, q_hi, Gq, st))) return rc;
     if ((rc = project_impl(hi->m, lo->m, R_hi, GR, st))) return rc;
     if ((rc = residual_impl(lo->m, Gq, R_lo, ws_lo, st))) return rc;
-    DG_HIP(launch_pack_pairs(lo->m.E, lo->m.n_p, Gq, GR, R_lo, x_out, y_out, st));
+    DG_HIP(launch_pack_pairs(lo->m.E, lo->m.n_p, 1.0, Gq, GR, R_lo, x_out, y_out, st));
+    return DG_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+size_t dg_increment_target_ws(const dg_mesh* hi, const dg_mesh* lo) {
+    if (!hi || !lo) return 0;
+    const size_t E = lo->m.E;
+    return 4 * align256(E * 5 * lo->m.n_p * sizeof(double)) + ws_layout(hi->m).total + ws_layout(lo->m).total;
+}
+
+int dg_increment_target(const dg_mesh* hi, const dg_mesh* lo, double* q_hi, double* k_hi, double dt_lo,
+                        int32_t m_sub, float* x_out, float* y_out, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_mesh(hi);
+    if (rc) return rc;
+    if ((rc = check_mesh(lo))) return rc;
+    if (hi->m.N != lo->m.N || lo->m.P > hi->m.P) return set_error(DG_EINVAL, "incompatible meshes");
+    if (!q_hi || !k_hi || q_hi == k_hi || !aligned8(q_hi) || !aligned8(k_hi) || !x_out || !y_out)
+        return set_error(DG_EINVAL, "bad pointers");
+    if (!(dt_lo > 0) || !std::isfinite(dt_lo)) return set_error(DG_EINVAL, "dt must be positive and finite");
+    if (m_sub < 1) return set_error(DG_EINVAL, "m_sub must be >= 1");
+    if (!ws || (((uintptr_t)ws) & 255)) return set_error(DG_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = dg_increment_target_ws(hi, lo);
+    if (ws_bytes < need) return set_error(DG_ENOSPC, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t fb = align256((size_t)lo->m.E * 5 * lo->m.n_p * sizeof(double));
+    char* p = (char*)ws;
+    double* q_nn = (double*)p;   p += fb;   // q_NN^n = G q_HO^n
+    double* q_nn1 = (double*)p;  p += fb;   // its uncorrected low-order step
+    double* k_lo = (double*)p;   p += fb;
+    double* qbar = (double*)p;   p += fb;   // G q_HO^{n+1}
+    char* ws_hi = p;             p += ws_layout(hi->m).total;
+    char* ws_lo = p;
+    if ((rc = project_impl(hi->m, lo->m, q_hi, q_nn, st))) return rc;
+    if ((rc = project_impl(hi->m, lo->m, q_hi, q_nn1, st))) return rc;
+    if ((rc = rk_impl(lo->m, q_nn1, k_lo, dt_lo, 1, nullptr, 0, ws_lo, st))) return rc;
+    if ((rc = rk_impl(hi->m, q_hi, k_hi, dt_lo / m_sub, m_sub, nullptr, 0, ws_hi, st))) return rc;
+    if ((rc = project_impl(hi->m, lo->m, q_hi, qbar, st))) return rc;
+    DG_HIP(launch_pack_pairs(lo->m.E, lo->m.n_p, dt_lo, q_nn, qbar, q_nn1, x_out, y_out, st));
     return DG_OK;
 }
 

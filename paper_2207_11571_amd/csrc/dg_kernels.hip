@@ -670,6 +670,7 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
         for (int v = 0; v < 5; ++v) {
             const double kk = first_stage ? D.dt * R[v] : rkA * D.k[v * vstride + node] + D.dt * R[v];
             qn[v] += rkB * kk;
+            if (D.post) qn[v] += D.dt * D.post[v * vstride + node];
             D.k[v * vstride + node] = kk;
             D.q[v * vstride + node] = qn[v];
         }
@@ -872,7 +873,7 @@ __global__ void __launch_bounds__(256) k_project(ProjArg pa, int E, const double
     }
 }
 
-__global__ void __launch_bounds__(256) k_pack_pairs(int E, int NP, const double* __restrict__ Gq,
+__global__ void __launch_bounds__(256) k_pack_pairs(int E, int NP, double div, const double* __restrict__ Gq,
                                                    const double* __restrict__ GR, const double* __restrict__ R3,
                                                    float* __restrict__ x, float* __restrict__ y) {
     const size_t total = (size_t)5 * E * NP;
@@ -883,15 +884,18 @@ __global__ void __launch_bounds__(256) k_pack_pairs(int E, int NP, const double*
         const size_t e = rem / NP, n = rem - e * NP;
         const size_t o = e * (5 * NP) + (size_t)v * NP + n;
         x[o] = (float)Gq[idx];
-        y[o] = (float)(GR[idx] - R3[idx]);
+        y[o] = (float)((GR[idx] - R3[idx]) / div);
     }
 }
 
-__global__ void k_write_descs(SolveDesc d0, SolveDesc d1, int n, SolveDesc* dev) {
-    if (threadIdx.x == 0) {
-        dev[0] = d0;
-        if (n > 1) dev[1] = d1;
-    }
+struct DescBatch {
+    SolveDesc d[4];
+};
+
+__global__ void k_write_descs(DescBatch b, int n, SolveDesc* dev) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (threadIdx.x == 0 && i < n) dev[i] = b.d[i];
 }
 
 // ------------------------------------------------------------ host launchers
@@ -901,8 +905,10 @@ hipError_t upload_basis_tables(const BasisTab* host_tabs) {
 }
 
 hipError_t launch_write_descs(const SolveDesc* host, int n, SolveDesc* dev, hipStream_t st) {
-    if (n < 1 || n > 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_write_descs, dim3(1), dim3(64), 0, st, host[0], n > 1 ? host[1] : host[0], n, dev);
+    if (n < 1 || n > 4) return hipErrorInvalidValue;
+    DescBatch b;
+    for (int i = 0; i < 4; ++i) b.d[i] = host[i < n ? i : 0];
+    hipLaunchKernelGGL(k_write_descs, dim3(1), dim3(64), 0, st, b, n, dev);
     return hipGetLastError();
 }
 
@@ -1002,12 +1008,12 @@ hipError_t launch_project(int PPs, int PPd, int E, const double* G1, const doubl
     }
 }
 
-hipError_t launch_pack_pairs(int E, int n_p, const double* Gq, const double* GR, const double* R3, float* x,
-                             float* y, hipStream_t st) {
+hipError_t launch_pack_pairs(int E, int n_p, double div, const double* Gq, const double* GR, const double* R3,
+                             float* x, float* y, hipStream_t st) {
     const size_t total = (size_t)5 * E * n_p;
     int blocks = (int)((total + 255) / 256);
     if (blocks > 65535) blocks = 65535;
-    hipLaunchKernelGGL(k_pack_pairs, dim3(blocks), dim3(256), 0, st, E, n_p, Gq, GR, R3, x, y);
+    hipLaunchKernelGGL(k_pack_pairs, dim3(blocks), dim3(256), 0, st, E, n_p, div, Gq, GR, R3, x, y);
     return hipGetLastError();
 }
 

@@ -49,6 +49,8 @@ struct SolveDesc {
     double* k;              // Runge-Kutta register [5][E][n_p]
     double* out;            // residual output [5][E][n_p] (residual mode)
     const double* forcing;  // s(q) [5][E][n_p] added to the residual, or null
+    const double* post;     // update mode: q += dt post after the stage update
+                            // (a post-step correction), or null
     const double* qtr_in;   // face traces of q   [E][6][5][n_f]
     double* qtr_out;        // face traces of the updated q (update mode)
     double* fv;             // one-sided viscous normal fluxes [E][6][4][n_f]
@@ -76,6 +78,10 @@ struct NetArgs {
     const uint16_t* WT[kMaxLayers];  // bf16 [pdims[l]][pdims[l+1]], zero padded
     const float* b[kMaxLayers];      // float32 [dims[l+1]]
     double mu_in[5], sig_in[5], mu_out[5], sig_out[5], mask[5];
+    // the network reads variables in_var[0..n_in) (input column j n_p + n is
+    // node n of variable in_var[j]) and forces out_var[0..n_out) likewise
+    int n_in, n_out;
+    int in_var[5], out_var[5];
 };
 
 // One network application target for the batched forcing kernel: the
@@ -125,7 +131,7 @@ hipError_t launch_err_inf(int PP, int E, const double* q, const double* qref, do
                           double* out, hipStream_t st);
 hipError_t launch_project(int PPs, int PPd, int E, const double* G1 /* host [PPd][PPs] */,
                           const double* src, double* dst, hipStream_t st);
-hipError_t launch_pack_pairs(int E, int n_p, const double* Gq, const double* GR, const double* R3,
+hipError_t launch_pack_pairs(int E, int n_p, double div, const double* Gq, const double* GR, const double* R3,
                              float* x, float* y, hipStream_t st);
 
 hipError_t launch_net_forcing(const NetArgs& na, int n_p, const NetTarget* targets, int nt,
@@ -140,8 +146,8 @@ int net_rows_per_block();
 // training: per-row-block forward / loss / backward data chain, then the
 // weight-gradient products reduced over the batch, then Adam
 struct TrainArgs {
-    const float* x;                   // [rows][dims[0]]
-    const float* y;                   // [rows][dims[L]]
+    const float* x;                   // [rows][5 n_p] (all variables)
+    const float* y;                   // [rows][5 n_p]
     const int32_t* idx;               // batch row b is row idx[b] (null: row b)
     int B, Bp;                        // batch, batch rounded up to 32
     float grad_scale;                 // 2 / (B * dims[L])

@@ -27,8 +27,6 @@ static int layout_dims(const int32_t* dims, int32_t n_layers, int* pd, int64_t* 
         if (dims[l] < 1 || dims[l] > 1024) return set_error(DG_EINVAL, "dims[%d] = %d outside [1, 1024]", l, dims[l]);
         pd[l] = pad32(dims[l]);
     }
-    if (dims[0] % 5 || dims[n_layers] % 5)
-        return set_error(DG_EINVAL, "input and output sizes must be 5 x nodes per element");
     int64_t np = 0, nb = 0;
     for (int l = 0; l < n_layers; ++l) {
         if (woff) woff[l] = np;
@@ -65,15 +63,19 @@ NetArgs net_args(const nn_model* m) {
         na.mu_out[v] = m->norm[10 + v];
         na.sig_out[v] = m->norm[15 + v];
         na.mask[v] = m->mask[v];
+        na.in_var[v] = m->in_var[v];
+        na.out_var[v] = m->out_var[v];
     }
+    na.n_in = m->n_in;
+    na.n_out = m->n_out;
     return na;
 }
 
 int net_check_mesh(const nn_model* m, const Mesh& mesh) {
     if (!m) return set_error(DG_EINVAL, "null model");
-    if (m->dims[0] != 5 * mesh.n_p || m->dims[m->n_layers] != 5 * mesh.n_p)
-        return set_error(DG_EINVAL, "network sizes %d -> %d do not match 5 x %d nodes per element", m->dims[0],
-                         m->dims[m->n_layers], mesh.n_p);
+    if (m->dims[0] != m->n_in * mesh.n_p || m->dims[m->n_layers] != m->n_out * mesh.n_p)
+        return set_error(DG_EINVAL, "network sizes %d -> %d do not match %d and %d variables x %d nodes per element",
+                         m->dims[0], m->dims[m->n_layers], m->n_in, m->n_out, mesh.n_p);
     if (m->device != mesh.device) return set_error(DG_EINVAL, "model and mesh live on different devices");
     return DG_OK;
 }
@@ -159,8 +161,26 @@ int nn_query(const int32_t* dims, int32_t n_layers, int64_t* n_params, int64_t* 
 
 int nn_init(const int32_t* dims, int32_t n_layers, int32_t activation, float* params, uint16_t* w_bf16, float* grad,
             float* adam_m, float* adam_v, const double* norm, const uint8_t* mask, void* stream, nn_model** out) {
+    return nn_init_io(dims, n_layers, activation, nullptr, nullptr, params, w_bf16, grad, adam_m, adam_v, norm, mask,
+                      stream, out);
+}
+
+int nn_init_io(const int32_t* dims, int32_t n_layers, int32_t activation, const uint8_t* in_vars,
+               const uint8_t* out_vars, float* params, uint16_t* w_bf16, float* grad, float* adam_m, float* adam_v,
+               const double* norm, const uint8_t* mask, void* stream, nn_model** out) {
     if (!out) return set_error(DG_EINVAL, "null output handle");
     *out = nullptr;
+    int iv[5], ov[5], n_in = 0, n_out = 0;
+    for (int v = 0; v < 5; ++v) {
+        if (!in_vars || in_vars[v]) iv[n_in++] = v;
+        if (!out_vars || out_vars[v]) ov[n_out++] = v;
+    }
+    if (n_in == 0 || n_out == 0) return set_error(DG_EINVAL, "the network must read and force at least one variable");
+    if (!dims || n_layers < 1 || n_layers > kMaxLayers) return set_error(DG_EINVAL, "bad dims or n_layers");
+    if (dims[0] < 1 || dims[n_layers] < 1 || dims[0] % n_in || dims[n_layers] % n_out ||
+        dims[0] / n_in != dims[n_layers] / n_out)
+        return set_error(DG_EINVAL, "input and output sizes must be %d and %d variables x the same node count", n_in,
+                         n_out);
     if (activation != 0 && activation != 1) return set_error(DG_EINVAL, "activation must be 0 (tanh) or 1 (relu)");
     if (!params || !w_bf16 || !norm) return set_error(DG_EINVAL, "null params, bf16 buffer or norm");
     if ((((uintptr_t)params) & 15) || (((uintptr_t)w_bf16) & 255))
@@ -177,6 +197,12 @@ int nn_init(const int32_t* dims, int32_t n_layers, int32_t activation, float* pa
     }
     m->n_layers = n_layers;
     m->act = activation;
+    m->n_in = n_in;
+    m->n_out = n_out;
+    for (int v = 0; v < 5; ++v) {
+        m->in_var[v] = v < n_in ? iv[v] : 0;
+        m->out_var[v] = v < n_out ? ov[v] : 0;
+    }
     for (int l = 0; l <= n_layers; ++l) m->dims[l] = dims[l];
     m->params = params;
     m->wbf = w_bf16;

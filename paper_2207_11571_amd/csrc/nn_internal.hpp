@@ -21,6 +21,9 @@ struct nn_model {
     int64_t wtbf_off[dgnn::kMaxLayers] = {0};// W_l^T offset in wbf
     double norm[20] = {0};
     double mask[5] = {1, 1, 1, 1, 1};
+    int n_in = 5, n_out = 5;                 // variables read / forced
+    int in_var[5] = {0, 1, 2, 3, 4};
+    int out_var[5] = {0, 1, 2, 3, 4};
     int64_t step = 0;                        // Adam step counter
     int device = 0;
 };

@@ -133,10 +133,22 @@ __global__ void __launch_bounds__(kRowThreads) k_net_forcing(NetArgs na, int NP,
         const int e = e0 + r;
         float x = 0.0f;
         if (e < E && c < din) {
-            const int v = c / NP, n = c - v * NP;
+            const int j = c / NP, n = c - j * NP;
+            const int v = na.in_var[j];
             x = (float)((T.q[v * vs + (size_t)e * NP + n] - na.mu_in[v]) / na.sig_in[v]);
         }
         bufA[r * ld + c] = f2bf(x);
+    }
+    // write mode: the variables the network does not force get s = 0
+    if (!accumulate && na.n_out < 5) {
+        for (int idx = t; idx < kRows * 5 * NP; idx += kRowThreads) {
+            const int r = idx / (5 * NP), c = idx - r * (5 * NP);
+            const int v = c / NP, n = c - v * NP;
+            const int e = e0 + r;
+            bool forced = false;
+            for (int j = 0; j < na.n_out; ++j) forced = forced || na.out_var[j] == v;
+            if (e < E && !forced) T.out[v * vs + (size_t)e * NP + n] = 0.0;
+        }
     }
     __syncthreads();
 
@@ -155,7 +167,8 @@ __global__ void __launch_bounds__(kRowThreads) k_net_forcing(NetArgs na, int NP,
                 const int e = e0 + m;
                 if (e < E && n < Nd) {
                     const float y = v + bias[n];
-                    const int vv = n / NP, node = n - vv * NP;
+                    const int j = n / NP, node = n - j * NP;
+                    const int vv = na.out_var[j];
                     const double s = na.mask[vv] * (na.sig_out[vv] * (double)y + na.mu_out[vv]);
                     double* o = T.out + vv * vs + (size_t)e * NP + node;
                     *o = accumulate ? *o + s : s;
@@ -214,15 +227,17 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
     const int wave = t >> 6, lane = t & 63;
     const int B = ta.B, Bp = ta.Bp;
     const int din = na.dims[0], pin = na.pdims[0];
-    const int npv_in = din / 5;
+    const int npv_in = din / na.n_in;
+    const size_t xw = (size_t)5 * npv_in;
     for (int idx = t; idx < kRows * pin; idx += kRowThreads) {
         const int r = idx / pin, c = idx - r * pin;
         const int row = r0 + r;
         float x = 0.0f;
         if (row < B && c < din) {
-            const int v = c / npv_in;
+            const int j = c / npv_in, n = c - j * npv_in;
+            const int v = na.in_var[j];
             const size_t src = ta.idx ? (size_t)ta.idx[row] : (size_t)row;
-            x = (float)((ta.x[src * din + c] - na.mu_in[v]) / na.sig_in[v]);
+            x = (float)((ta.x[src * xw + (size_t)v * npv_in + n] - na.mu_in[v]) / na.sig_in[v]);
         }
         act[0][r * ld + c] = f2bf(x);
     }
@@ -244,15 +259,18 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
     {
         const int l = L - 1;
         const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
-        const int npv_out = Nd / 5;
+        const int npv_out = Nd / na.n_out;
+        const size_t yw = (size_t)5 * npv_out;
         const float* bias = na.b[l];
         tile_mma(act[l], ld, na.W[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
             const int row = r0 + m;
             float dy = 0.0f;
             if (row < B && n < Nd) {
-                const int vv = n / npv_out;
+                const int j = n / npv_out, nn = n - j * npv_out;
+                const int vv = na.out_var[j];
                 const size_t src = ta.idx ? (size_t)ta.idx[row] : (size_t)row;
-                const float yt = (float)((ta.y[src * Nd + n] - na.mu_out[vv]) / na.sig_out[vv]);
+                const float yt =
+                    (float)((ta.y[src * yw + (size_t)vv * npv_out + nn] - na.mu_out[vv]) / na.sig_out[vv]);
                 const float diff = v + bias[n] - yt;
                 lsum += diff * diff;
                 dy = ta.grad_scale * diff;

@@ -1,0 +1,233 @@
+"""GPU parity of Algorithm 1's pieces against the CPU oracle, through the C
+ABI: the discrete-increment training pairs (dg_increment_target), the
+post-step corrected low-order evolution (dg_rk_step_post) and a network that
+reads and forces the three momenta only (nn_init_io).
+
+Tolerances: the pairs are float32 rows of float64 arithmetic, 1e-6 relative
+(L2 per array); the advanced high-order state 1e-12 relative; the network
+parts as the other network tests (bf16 matrix cores): forcing and gradients
+1e-2 relative, kinetic-energy history 1e-3 relative.  For the relu network's
+gradients the oracle stores its activations as bfloat16 like the device, so
+that both take relu's derivative decisions on the same values.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from helpers import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MOM = (1, 2, 3)
+# momentum in, momentum out, relu: the paper's network shape at P = 3
+DIMS = [192, 256, 256, 256, 192]
+NORM = [1.0, 0.0, 0.0, 0.0, synthetic.TGV_ENERGY_LEVEL,
+        0.01, 1.0, 1.0, 1.0, 1.0,
+        0.0, 0.0, 0.0, 0.0, 0.0,
+        1e-2, 1e-2, 1e-2, 1e-2, 1e-2]
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_11571_amd import binding
+    binding.lib()
+    return binding
+
+
+def _to_gpu(a, dtype=np.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def _state(N, P, Re, seed):
+    """TGV plus a smooth perturbation of every variable (oracle IC)."""
+    from oracle import dg
+    prm = dg.Params(N=N, P=P, Re=Re)
+    q = dg.tgv_initial_condition(prm)
+    x = dg.node_coordinates(prm)
+    a = np.random.default_rng(seed).uniform(0.02, 0.05, size=5)
+    for v in range(5):
+        q[v] = q[v] + (1.0 if v < 4 else 10.0) * a[v] * np.sin(x[0] + 2 * x[1] + v) * np.cos(x[2] - v)
+    return prm, q
+
+
+def _oracle_model(layers, norm=NORM):
+    from oracle import forcing, mlp
+    params = [(mlp.bf16_round(W), b.astype(np.float64)) for W, b in layers]
+    return params, forcing.Normalisation(norm[0:5], norm[5:10], norm[10:15], norm[15:20])
+
+
+@pytest.mark.parametrize("P_hi,m_sub", [(5, 2), (8, 3)])
+def test_increment_target_matches_oracle(B, P_hi, m_sub):
+    from oracle import dg, forcing
+    say("increment target", P_hi, m_sub)
+    N, P_lo, Re, dt = 2, 3, 400.0, 1e-3
+    prm_hi, q = _state(N, P_hi, Re, seed=P_hi)
+    prm_lo = dg.Params(N=N, P=P_lo, Re=Re)
+    x_ref, y_ref, q1_ref = forcing.increment_target(q, prm_hi, prm_lo, dt, m_sub)
+    hi, lo = B.Mesh(N, P_hi, Re), B.Mesh(N, P_lo, Re)
+    qg = _to_gpu(dg.to_flat(q))
+    kg = hi.field(0.0)
+    E = N ** 3
+    X = torch.empty((E, 5 * 64), dtype=torch.float32, device="cuda")
+    Y = torch.empty_like(X)
+    B.dg_increment_target(hi, lo, qg, kg, dt, m_sub, X, Y)
+    torch.cuda.synchronize()
+    ex, ey = rel_l2(X.cpu().numpy(), x_ref), rel_l2(Y.cpu().numpy(), y_ref)
+    eq = rel_l2(qg.cpu().numpy(), dg.to_flat(q1_ref))
+    print("x", ex, "y", ey, "q_hi", eq)
+    assert ex < 1e-6 and ey < 1e-6 and eq < 1e-12
+
+
+def test_post_corrected_steps_match_oracle(B):
+    """20 steps of Algorithm 1's low-order evolution (uncorrected step, then
+    + dt s(q^n)) with a momentum-only relu network, P = 3 on 4^3 elements."""
+    from oracle import dg, forcing, rk
+    say("post-corrected steps")
+    N, P, Re, steps = 4, 3, 400.0, 20
+    layers = synthetic.mlp_init(DIMS, seed=1)
+    layers = [(W, b + 0.02) for W, b in layers]
+    params, norm = _oracle_model(layers)
+    prm = dg.Params(N=N, P=P, Re=Re)
+    q0 = dg.tgv_initial_condition(prm)
+    dt = dg.stable_dt(q0, prm)
+    q_ref, q_unc = q0, q0
+    ke_ref = []
+    for n in range(steps):
+        q_ref = forcing.post_corrected_step(q_ref, prm, dt, params, norm, "relu", MOM, MOM)
+        ke_ref.append(dg.kinetic_energy(q_ref, prm))
+    q_unc = rk.integrate(q0, dt, steps, lambda qq, t: dg.residual(qq, prm))
+    m = B.Mesh(N, P, Re)
+    model = B.Model(DIMS, B.pack_params(layers), NORM, activation="relu", train=False, in_vars=MOM, out_vars=MOM)
+    m.ws.fill_(0x7F)     # garbage in the forcing buffer: the network's write must clear it
+    q = _to_gpu(dg.to_flat(q0))
+    k = m.field(0.0)
+    ke = []
+    for n in range(steps):
+        B.dg_rk_step_post(m, q, k, dt, 1, model=model)
+        ke.append(B.dg_diagnostics(m, q)[0].item())
+    ke, ke_ref = np.array(ke), np.array(ke_ref)
+    e_ke = np.max(np.abs(ke - ke_ref) / ke_ref)
+    got = q.cpu().numpy()
+    corr_ref = dg.to_flat(q_ref) - dg.to_flat(q_unc)
+    e_corr = rel_l2(got - dg.to_flat(q_unc), corr_ref)
+    print("KE history max rel", e_ke, "accumulated correction rel L2", e_corr)
+    assert e_ke < 1e-3 and e_corr < 2e-2
+    # without a model the post-corrected stepper is the plain one, bitwise
+    qa, qb = _to_gpu(dg.to_flat(q0)), _to_gpu(dg.to_flat(q0))
+    B.dg_rk_step_post(m, qa, k, dt, 3)
+    B.dg_rk_step(m, qb, k, dt, 3)
+    assert torch.equal(qa, qb)
+
+
+def test_post_correction_is_dt_times_forcing_of_the_step_start(B):
+    """One post-corrected step minus one plain step is dt s(q^n), s from
+    nn_forcing on the starting state (GPU against GPU: one rounding)."""
+    from oracle import dg
+    say("post correction = dt s(q^n)")
+    N, P, Re = 3, 3, 400.0
+    layers = synthetic.mlp_init(DIMS, seed=2)
+    prm, q0 = _state(N, P, Re, seed=5)
+    m = B.Mesh(N, P, Re)
+    model = B.Model(DIMS, B.pack_params(layers), NORM, activation="relu", train=False, in_vars=MOM, out_vars=MOM)
+    dt = 1e-3
+    qa, qb = _to_gpu(dg.to_flat(q0)), _to_gpu(dg.to_flat(q0))
+    k = m.field(0.0)
+    s = m.field(0.0)
+    B.nn_forcing(model, m, qa, s)
+    B.dg_rk_step_post(m, qa, k, dt, 1, model=model)
+    B.dg_rk_step(m, qb, k, dt, 1)
+    torch.cuda.synchronize()
+    d = (qa - qb).cpu().numpy()
+    ref = dt * s.cpu().numpy()
+    assert np.max(np.abs(d - ref)) < 1e-12 * np.max(np.abs(qb.cpu().numpy()))
+    assert not s[0].any() and not s[4].any() and s[1:4].abs().max() > 0
+
+
+def test_momentum_network_forcing_and_gradients(B):
+    """nn_init_io network (momenta in and out): forcing vs the oracle's
+    selected-variable network; one training step's gradients vs the oracle on
+    the momentum columns of full five-variable rows."""
+    from oracle import dg, forcing, mlp
+    say("momentum network")
+    layers = synthetic.mlp_init(DIMS, seed=3)
+    layers = [(W, b + 0.01) for W, b in layers]
+    params, norm = _oracle_model(layers)
+    prm, q = _state(3, 3, 400.0, seed=6)
+    qf = dg.to_flat(q)
+    ref = forcing.network_forcing(qf, params, norm, "relu", MOM, MOM)
+    m = B.Mesh(3, 3, 400.0)
+    model = B.Model(DIMS, B.pack_params(layers), NORM, activation="relu", in_vars=MOM, out_vars=MOM)
+    out = m.field(0.0)
+    B.nn_forcing(model, m, _to_gpu(qf), out)
+    got = out.cpu().numpy()
+    err = rel_l2(got, ref)
+    print("forcing rel L2", err)
+    assert err < 1e-2 and not got[[0, 4]].any()
+    # one training step on full rows
+    batch, n_p = 256, 64
+    rng = np.random.default_rng(7)
+    x = np.empty((batch, 320), dtype=np.float32)
+    x[:, :64] = 1.0 + 0.01 * rng.standard_normal((batch, 64))
+    x[:, 64:256] = rng.standard_normal((batch, 192))
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((batch, 64))
+    y = (1e-2 * rng.standard_normal((batch, 320))).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    B.nn_train_step(model, _to_gpu(x, np.float32), _to_gpu(y, np.float32), lr=1e-3, loss=loss)
+    torch.cuda.synchronize()
+    mi, si = np.repeat(norm.mu_in[list(MOM)], n_p), np.repeat(norm.sigma_in[list(MOM)], n_p)
+    mo, so = np.repeat(norm.mu_out[list(MOM)], n_p), np.repeat(norm.sigma_out[list(MOM)], n_p)
+    xh = (x[:, 64:256].astype(np.float64) - mi) / si
+    yt = (y[:, 64:256].astype(np.float64) - mo) / so
+    # relu's derivative is a decision on the hidden outputs: the oracle takes it
+    # on the same bfloat16-stored activations as the device network
+    loss_ref, grads = mlp.mse_loss_and_grads(params, xh, yt, "relu", quantise=True)
+    assert abs(loss.item() / loss_ref - 1) < 1e-2
+    g_gpu = B.unpack_params(model.grad.cpu().numpy().astype(np.float64), DIMS)
+    for l, ((gW, gb), (rW, rb)) in enumerate(zip(g_gpu, grads)):
+        eW, eb = rel_l2(gW, rW), rel_l2(gb, rb)
+        print("layer", l, "grad rel L2", eW, eb)
+        assert eW < 1e-2 and eb < 1e-2
+
+
+def test_io_selection_rejects_bad_sizes(B):
+    say("io selection errors")
+    layers = synthetic.mlp_init([320, 64, 192], seed=0)
+    with pytest.raises(B.DGError):
+        B.Model([320, 64, 192], B.pack_params(layers), NORM, in_vars=MOM, out_vars=MOM, train=False)
+    layers = synthetic.mlp_init([192, 64, 192], seed=0)
+    model = B.Model([192, 64, 192], B.pack_params(layers), NORM, in_vars=MOM, out_vars=MOM, train=False)
+    m = B.Mesh(2, 2, 400.0)        # 27 nodes: 192 is not 3 x 27
+    with pytest.raises(B.DGError):
+        B.nn_forcing(model, m, m.field(1.0), m.field(0.0))
+
+
+def test_stage_forcing_with_momentum_network(B):
+    """The per-stage corrected stepper (Eq. (4)) with a momentum-only network:
+    the unforced variables get no forcing and the accumulated correction
+    matches the oracle's."""
+    from oracle import dg, forcing, rk
+    say("per-stage forcing, momentum network")
+    N, P, Re, steps = 3, 3, 400.0, 10
+    layers = synthetic.mlp_init(DIMS, seed=4)
+    layers = [(W, b + 0.02) for W, b in layers]
+    params, norm = _oracle_model(layers)
+    prm, q0 = _state(N, P, Re, seed=8)
+    dt = dg.stable_dt(q0, prm)
+    q_ref = rk.integrate(q0, dt, steps, lambda qq, t: forcing.corrected_rhs(qq, prm, params, norm, "relu",
+                                                                            None, MOM, MOM))
+    q_unc = rk.integrate(q0, dt, steps, lambda qq, t: dg.residual(qq, prm))
+    m = B.Mesh(N, P, Re)
+    model = B.Model(DIMS, B.pack_params(layers), NORM, activation="relu", train=False, in_vars=MOM, out_vars=MOM)
+    # leave garbage in the workspace's forcing buffer: the write must clear it
+    m.ws.fill_(0x7F)
+    q = _to_gpu(dg.to_flat(q0))
+    k = m.field(0.0)
+    B.dg_rk_step(m, q, k, dt, steps, model=model)
+    got = q.cpu().numpy()
+    corr_ref = dg.to_flat(q_ref) - dg.to_flat(q_unc)
+    e_corr = rel_l2(got - dg.to_flat(q_unc), corr_ref)
+    print("accumulated correction rel L2", e_corr)
+    assert e_corr < 2e-2

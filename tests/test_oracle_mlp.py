@@ -143,3 +143,25 @@ def test_forcing_target_is_conservative():
         scale = np.sum(dg.quadrature_weights(Basis(6)) * prm_hi.J * np.abs(R_hi[v]))
         assert abs(np.sum(Wq * yb[v])) < 1e-13 * max(scale, 1.0)
     assert np.max(np.abs(dg.to_blocks(forcing.rows_to_field(x, 5, 64), 2, 3) - projection.project(q, 6, 3))) == 0
+
+
+def test_quantised_forward_stores_bf16_and_is_exact_on_representable_values():
+    """quantise=True rounds the input and the hidden outputs to bfloat16: every
+    stored activation is a bfloat16 value, and a network whose activations are
+    small integers (exact in bfloat16) gives the unquantised result."""
+    rng = np.random.default_rng(13)
+    params, x, _ = _tiny(6)
+    outs = mlp.forward(params, x, "tanh", quantise=True)
+    for h in outs[:-1]:
+        assert np.array_equal(mlp.bf16_round(h), h)
+    # integer weights, integer inputs, relu: activations stay small integers
+    dims = (6, 5, 4, 3)
+    ip = [(rng.integers(-2, 3, size=(dims[l + 1], dims[l])).astype(np.float64),
+           rng.integers(-2, 3, size=dims[l + 1]).astype(np.float64)) for l in range(3)]
+    xi = rng.integers(-3, 4, size=(7, 6)).astype(np.float64)
+    a = mlp.forward(ip, xi, "relu", quantise=True)
+    b = mlp.forward(ip, xi, "relu")
+    assert all(np.array_equal(u, v) for u, v in zip(a, b))
+    la, ga = mlp.mse_loss_and_grads(ip, xi, np.zeros((7, 3)), "relu", quantise=True)
+    lb, gb = mlp.mse_loss_and_grads(ip, xi, np.zeros((7, 3)), "relu")
+    assert la == lb and all(np.array_equal(p[0], q[0]) and np.array_equal(p[1], q[1]) for p, q in zip(ga, gb))
