@@ -241,18 +241,24 @@ def main():
         log("accuracy-time study (8^3)")
         from paper_2207_11571_amd import study as st
         res = st.run_study(N=8, Re=1600.0, t0=4.0, window=0.15, snapshots=100, eval_end=4.45, batch=512,
-                           orders=(5, 6), variants=[("nn", (1, 1, 1, 1, 1), 200, 1e-3)], log=lambda *a: None)
+                           orders=(5, 6), variants=[st.variant("nn", epochs=200),
+                                                    st.variant("alg1", "alg1", "momentum", "relu", "post", epochs=200),
+                                                    st.variant("alg1a", "alg1", "all", "tanh", "post", epochs=200)],
+                           log=lambda *a: None)
         runs = res["runs"]
-        study = {"config": "8^3 elements, Re 1600, P=8 reference from t=0; pairs (Eq. 5) every 0.0015 over "
-                           "[4, 4.15]; 200 epochs Adam batch 512; evaluation to t=4.45; e_n = max momentum "
-                           "error vs filtered P=8 (Eq. 9) on the P=3 space",
-                 "training_s": res["training"]["variants"]["nn"]["seconds"],
+        study = {"config": "8^3 elements, Re 1600, P=8 reference from t=0; training pairs every 0.0015 (one P=3 "
+                           "step) over [4, 4.15]: 'nn' Eq. (5) pairs, all variables, tanh, forcing every stage; "
+                           "'alg1' Algorithm 1 increments, momentum in/out, relu, correction after each step; "
+                           "'alg1a' Algorithm 1 increments and correction, all variables, tanh; 200 epochs Adam "
+                           "batch 512; evaluation to t=4.45; e_n = max momentum error vs filtered P=8 (Eq. 9) "
+                           "on the P=3 space",
+                 "training_s": {k: v["seconds"] for k, v in res["training"]["variants"].items()},
                  "reference_p8_s": res["reference"]["seconds_to_t0"] + res["reference"]["seconds_window_and_eval"]}
-        for name in ("P3", "P3+nn", "P5", "P6"):
+        for name in ("P3", "P3+nn", "P3+alg1", "P3+alg1a", "P5", "P6"):
             r = runs[name]
             study[name] = {"mean_e_window": r["mean_e_window"], "mean_e_beyond": r["mean_e_beyond"],
                            "wall_per_unit_time_s": r["wall_per_unit_time_s"], "dt": r["dt"]}
-        study["p6_wall_over_p3nn"] = runs["P6"]["wall_s"] / runs["P3+nn"]["wall_s"]
+        study["p6_wall_over_p3nn"] = {k: runs["P6"]["wall_s"] / runs["P3+" + k]["wall_s"] for k in ("nn", "alg1", "alg1a")}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -1,13 +1,18 @@
-"""The learned part end to end on the GPU (Sec. 2.1 three steps, Sec. 3.3
-time frame t = 4 at Re 1600, Sec. 3.4 accuracy vs order): the project's own
-P = 8 run generates the Eq. (5) pairs, the network is trained on the device
-by the library's forward / backward / Adam kernels, and the corrected P = 3
-run is compared with the uncorrected P = 3 and with plain P = 6, all errors
-measured against the filtered P = 8 solution (Eq. (9)).
+"""The learned part end to end on the GPU (Sec. 2.1 three steps, Algorithm 1,
+Sec. 3.3 time frame t = 4 at Re 1600, Sec. 3.4 accuracy vs order): the
+project's own P = 8 run generates the training pairs, the networks are
+trained on the device by the library's forward / backward / Adam kernels,
+and the corrected P = 3 runs are compared with the uncorrected P = 3 and
+with plain P = 6, all errors measured against the filtered P = 8 solution
+(Eq. (9)).
 
 Configuration: the paper's mesh (8^3 elements), P_HO = 8, P_LO = 3,
 training window of 0.15 time units from t = 4 with one snapshot every
-0.0015 (about one low-order step), 200 epochs of Adam (batch 512).
+0.0015 (one low-order step), 200 epochs of Adam (batch 512).  Three
+networks: "nn" (Eq. (5) pairs, all five variables, tanh, forcing at every
+stage), "alg1" (the paper's form: Algorithm 1's discrete-increment pairs,
+momentum in and out, relu, correction after each step) and "alg1a"
+(Algorithm 1's pairs and correction, all five variables, tanh).
 """
 import numpy as np
 import pytest
@@ -25,12 +30,15 @@ def study():
     from paper_2207_11571_amd import study as st
     say("learned forcing study 8^3")
     return st.run_study(N=8, Re=1600.0, t0=4.0, window=0.15, snapshots=100, eval_end=4.45, batch=512,
-                        orders=(6,), variants=[("nn", (1, 1, 1, 1, 1), 200, 1e-3)],
+                        orders=(6,), variants=[st.variant("nn", epochs=200),
+                                               st.variant("alg1", "alg1", "momentum", "relu", "post", epochs=200),
+                                               st.variant("alg1a", "alg1", "all", "tanh", "post", epochs=200)],
                         log=lambda *a: print("[study]", *a, flush=True))
 
 
-def test_training_converges(study):
-    losses = study["training"]["variants"]["nn"]["loss_per_epoch"]
+@pytest.mark.parametrize("name", ["nn", "alg1", "alg1a"])
+def test_training_converges(study, name):
+    losses = study["training"]["variants"][name]["loss_per_epoch"]
     assert np.all(np.isfinite(losses))
     assert losses[-1] < 1e-2 * losses[0]
 
@@ -51,3 +59,24 @@ def test_trained_forcing_gains_over_uncorrected_p3(study):
     # ... and as close as plain P = 6, for less wall time per unit of physical time
     assert nn["mean_e_window"] <= 1.2 * p6["mean_e_window"]
     assert nn["wall_s"] < p6["wall_s"]
+
+
+def test_algorithm1_forcing_gains(study):
+    """Algorithm 1 (discrete-increment pairs, correction after each step): the
+    paper's momentum network stays closer to the filtered P = 8 solution than
+    uncorrected P = 3 over the whole evaluation span; with all five variables
+    the corrected P = 3 run is as accurate as plain P = 6 in the window, in
+    less wall time."""
+    p3, p6 = study["runs"]["P3"], study["runs"]["P6"]
+    a1, a1a = study["runs"]["P3+alg1"], study["runs"]["P3+alg1a"]
+    print("mean e_n in window: P3 %.3e  alg1 %.3e  alg1a %.3e  P6 %.3e" % (
+        p3["mean_e_window"], a1["mean_e_window"], a1a["mean_e_window"], p6["mean_e_window"]))
+    print("mean e_n beyond:    P3 %.3e  alg1 %.3e  alg1a %.3e  P6 %.3e" % (
+        p3["mean_e_beyond"], a1["mean_e_beyond"], a1a["mean_e_beyond"], p6["mean_e_beyond"]))
+    print("wall per unit time: alg1 %.3f  alg1a %.3f  P6 %.3f s" % (
+        a1["wall_per_unit_time_s"], a1a["wall_per_unit_time_s"], p6["wall_per_unit_time_s"]))
+    assert a1["mean_e_window"] < 0.5 * p3["mean_e_window"]
+    assert a1["mean_e_beyond"] < 0.8 * p3["mean_e_beyond"]
+    assert study["gain"]["alg1"]["better_than_p3_until"] >= 4.3
+    assert a1a["mean_e_window"] <= p6["mean_e_window"]
+    assert a1a["wall_s"] < p6["wall_s"] and a1["wall_s"] < p6["wall_s"]
