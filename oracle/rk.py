@@ -1,5 +1,5 @@
-"""Three-stage, third-order low-storage Runge-Kutta time integration (Sec. 3.1:
-"third-order three-stage Runge-Kutta scheme"; Eq. (6) is its one-stage analogue).
+"""Three-stage, third-order low-storage Runge-Kutta time integration (Sec. 3.1
+names a third-order scheme with three stages; Eq. (6) is its one-stage analogue).
 
 Test infrastructure only (see ``oracle/__init__``).
 
