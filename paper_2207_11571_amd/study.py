@@ -1,27 +1,32 @@
 """Learned corrective forcing on one GPU, end to end (Sec. 2.1 three steps,
-Algorithm 1, Sec. 3.3 time frames, Sec. 3.4 effective acceleration / Table 2).
+Algorithm 1, Sec. 3.3 time frames, Sec. 3.4 effective acceleration / Table 2,
+Sec. 3.5 transfer learning).
 
 1. High-order evolution: P = 8 Taylor-Green run from t = 0; over the training
    window, at every snapshot interval dT the training pairs are appended to a
    device dataset, in one or both of two forms:
      "eq5":  the instantaneous target of Eq. (5), x = G q_8, y = G p_8(q_8) -
-             p_3(G q_8), at the end of the interval;
-     "alg1": Algorithm 1's discrete increment over one low-order step dT,
-             x = G q_8(t), y = (G q_8(t + dT) - q_3(t + dT)) / dT, q_3 the
+             p_LO(G q_8), at the end of the interval;
+     "alg1": Algorithm 1's discrete increment over each low-order step dt,
+             x = G q_8(t), y = (G q_8(t + dt) - q_LO(t + dt)) / dt, q_LO the
              uncorrected low-order step from G q_8(t).
    The filtered reference G q_8(t) is kept for the error of Eq. (9).
 2. Training: the per-variable normalisation of the dataset, then epochs of
    shuffled minibatches of Adam on the MSE loss, on the GPU, for each network
-   variant (target form, variables read and forced, activation).
-3. Low-order evolution from G q_8(t0): P = 3 without and with each network --
-   "stage" variants force every Runge-Kutta stage (Eq. (4)), "post" variants
-   correct after each uncorrected step as Algorithm 1 does -- and plain
-   P = 4, 5, 6 for the accuracy-time comparison.  All errors are measured on
-   the P = 3 space: e_n = max |G_{P->3} q_P - G_{8->3} q_8| over the three
-   momenta (Eq. (9)).
+   variant (target form, variables read and forced, activation), from a
+   Gaussian initialisation or from another network's weights (retraining).
+3. Low-order evolution from G q_8(t0): the low order without and with each
+   network -- "stage" variants force every Runge-Kutta stage (Eq. (4)),
+   "post" variants correct after each uncorrected step as Algorithm 1 does --
+   and plain higher orders for the accuracy-time comparison.  All errors are
+   measured on the low-order space: e_n = max |G_{P->LO} q_P - G_{8->LO} q_8|
+   over the three momenta (Eq. (9)).
 
-Every step runs in libdgnn.so; this driver only sequences calls and keeps
-time.  ``python -m paper_2207_11571_amd.study --help``.
+``run_study`` is one time frame; ``run_transfer`` trains on one frame (or
+Reynolds number) and applies the network to another directly, after a short
+retraining from its weights, and against a network trained there from
+scratch.  Every step runs in libdgnn.so; this driver only sequences calls
+and keeps time.  ``python -m paper_2207_11571_amd.study --help``.
 """
 import argparse
 import json
@@ -36,6 +41,7 @@ from . import binding as B
 HIDDEN = [256, 256, 256]
 MOMENTUM = (1, 2, 3)
 ALL = (0, 1, 2, 3, 4)
+P_HO = 8
 
 
 def _sync():
@@ -50,177 +56,291 @@ def variant(name, target="eq5", io="all", act="tanh", mode="stage", epochs=30, l
     return dict(name=name, target=target, io=io, act=act, mode=mode, epochs=epochs, lr=lr, mask=tuple(mask))
 
 
+class Reference:
+    """A P = 8 Taylor-Green run from t = 0 at one Reynolds number, advanced on
+    demand with a fixed step (from the initial state: dT / n_hi)."""
+
+    def __init__(self, N, Re, dT, P_lo, cfl=0.4):
+        self.N, self.Re, self.dT, self.P_lo = N, Re, dT, P_lo
+        self.m_hi, self.m_lo = B.Mesh(N, P_HO, Re), B.Mesh(N, P_lo, Re)
+        self.q = self.m_hi.field()
+        B.dg_init_tgv(self.m_hi, self.q)
+        q_lo = self.m_lo.field()
+        B.dg_project(self.m_hi, self.m_lo, self.q, q_lo)
+        # low-order steps per interval; high-order steps a multiple of them
+        self.n_lo = math.ceil(dT / B.dg_stable_dt(self.m_lo, q_lo, cfl) - 1e-12)
+        dt_hi = B.dg_stable_dt(self.m_hi, self.q, cfl)
+        self.n_hi = self.n_lo * math.ceil(dT / self.n_lo / dt_hi - 1e-12)
+        self.dt_hi = dT / self.n_hi
+        self.k = self.m_hi.field(0.0)
+        self.steps = 0          # intervals dT advanced
+        self.seconds = 0.0
+
+    @property
+    def t(self):
+        return self.steps * self.dT
+
+    def advance_to(self, t_target):
+        n = int(round(t_target / self.dT)) - self.steps
+        if n < 0:
+            raise ValueError("the reference cannot go back in time")
+        _sync()
+        ta = time.perf_counter()
+        if n:
+            B.dg_rk_step(self.m_hi, self.q, self.k, self.dt_hi, n * self.n_hi)
+        _sync()
+        self.seconds += time.perf_counter() - ta
+        self.steps += n
+        self.check()
+
+    def check(self):
+        d = B.dg_diagnostics(self.m_hi, self.q).cpu().numpy()
+        if not np.all(np.isfinite(d)) or not d[2] > 0:
+            raise FloatingPointError(f"P{P_HO} reference at Re={self.Re:g} is no longer finite at t={self.t:g}")
+
+    def window(self, snapshots, n_eval, targets, orders=(), log=print):
+        """From the current time: training pairs over the first `snapshots`
+        intervals and the filtered reference over n_eval intervals."""
+        m_hi, m_lo = self.m_hi, self.m_lo
+        E, n_p = m_lo.E, m_lo.n_p
+        t0 = self.t
+        data = {}
+        for tg in targets:
+            rows = snapshots * E * (self.n_lo if tg == "alg1" else 1)
+            data[tg] = (torch.empty((rows, 5 * n_p), dtype=torch.float32, device="cuda"),
+                        torch.empty((rows, 5 * n_p), dtype=torch.float32, device="cuda"))
+        ref = torch.empty((n_eval + 1, 5, E, n_p), dtype=torch.float64, device="cuda")
+        init = {}
+        for P in orders:
+            m = B.Mesh(self.N, P, self.Re)
+            f = m.field()
+            B.dg_project(m_hi, m, self.q, f)
+            init[P] = (m, f)
+        B.dg_project(m_hi, m_lo, self.q, ref[0])
+        ws_eq5 = ws_alg1 = None
+        _sync()
+        ta = time.perf_counter()
+        for j in range(1, n_eval + 1):
+            if j <= snapshots and "alg1" in data:
+                X, Y = data["alg1"]
+                for i in range(self.n_lo):
+                    r0 = ((j - 1) * self.n_lo + i) * E
+                    ws_alg1 = B.dg_increment_target(m_hi, m_lo, self.q, self.k, self.dT / self.n_lo,
+                                                     self.n_hi // self.n_lo, X[r0:r0 + E], Y[r0:r0 + E], ws=ws_alg1)
+            else:
+                B.dg_rk_step(m_hi, self.q, self.k, self.dt_hi, self.n_hi)
+            B.dg_project(m_hi, m_lo, self.q, ref[j])
+            if j <= snapshots and "eq5" in data:
+                X, Y = data["eq5"]
+                ws_eq5 = B.dg_forcing_target(m_hi, m_lo, self.q, X[(j - 1) * E:j * E], Y[(j - 1) * E:j * E],
+                                             ws=ws_eq5)
+        _sync()
+        t_gen = time.perf_counter() - ta
+        self.seconds += t_gen
+        self.steps += n_eval
+        self.check()
+        log(f"P{P_HO} Re={self.Re:g} window from t={t0:g}: {t_gen:.2f}s, datasets " +
+            ", ".join(f"{k} {tuple(v[0].shape)}" for k, v in data.items()))
+        return {"t0": t0, "data": data, "ref": ref, "init": init, "seconds": t_gen, "n_eval": n_eval,
+                "snapshots": snapshots}
+
+
+def train(X, Y, n_p, v, batch, seed=0, norm=None, init_params=None, log=print):
+    """Trains one network variant on rows (X, Y); returns (model, norm,
+    record).  norm: normalisation (default: the dataset's statistics);
+    init_params: float32 device tensor of weights to start from (default:
+    Gaussian)."""
+    import synthetic
+    rows = X.shape[0]
+    nb = rows // batch
+    io = MOMENTUM if v["io"] == "momentum" else ALL
+    dims = [len(io) * n_p] + HIDDEN + [len(io) * n_p]
+    flops = 3 * 2 * sum(a * b for a, b in zip(dims[:-1], dims[1:])) * batch
+    if norm is None:
+        norm = B.nn_data_stats(X, Y, n_p)
+    params = init_params.clone() if init_params is not None else B.pack_params(synthetic.mlp_init(dims, seed=seed))
+    model = B.Model(dims, params, norm, mask=v["mask"], activation=v["act"], in_vars=io, out_vars=io)
+    rng = np.random.default_rng(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    losses = []
+    _sync()
+    ta = time.perf_counter()
+    for ep in range(v["epochs"]):
+        perm = torch.from_numpy(synthetic.epoch_permutation(rows, rng).astype(np.int32)).cuda()
+        ep_loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for b in range(nb):
+            B.nn_train_step(model, X, Y, lr=v["lr"], loss=loss, idx=perm[b * batch:(b + 1) * batch])
+            ep_loss += loss
+        losses.append(float(ep_loss.item()) / nb)
+    _sync()
+    t_train = time.perf_counter() - ta
+    rec = {**v, "pairs": rows, "batches_per_epoch": nb, "dims": dims, "seconds": t_train, "norm": list(norm),
+           "steps_per_s": v["epochs"] * nb / t_train if t_train > 0 else None,
+           "tflops": v["epochs"] * nb * flops / t_train / 1e12 if t_train > 0 else None,
+           "loss_per_epoch": losses, "from_weights": init_params is not None}
+    if losses:
+        log(f"training {v['name']} ({v['target']} pairs, {v['io']}, {v['act']}, {v['mode']}"
+            f"{', from given weights' if init_params is not None else ''}): {v['epochs']} epochs x {nb} batches "
+            f"in {t_train:.2f}s, loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    return model, norm, rec
+
+
+def evolve(ref, win, mesh, q0, window, model=None, mode="stage", cfl=0.4):
+    """Low- or high-order run from q0 over the window's evaluation span; e_n
+    against the filtered reference on the low-order space."""
+    m_lo, dT, n_eval = ref.m_lo, ref.dT, win["n_eval"]
+    q = q0.clone()
+    k = mesh.field(0.0)
+    n = ref.n_lo if mesh.P == ref.P_lo else math.ceil(dT / B.dg_stable_dt(mesh, q, cfl) - 1e-12)
+    dt = dT / n
+    step = B.dg_rk_step_post if mode == "post" else B.dg_rk_step
+    tmp = m_lo.field()
+    err = torch.empty(3, dtype=torch.float64, device="cuda")
+    errs = []
+    wall = 0.0
+    for j in range(n_eval + 1):
+        if j > 0:
+            _sync()
+            ta = time.perf_counter()
+            step(mesh, q, k, dt, n, model=model)
+            _sync()
+            wall += time.perf_counter() - ta
+        if mesh.P == ref.P_lo:
+            B.dg_error_inf(mesh, q, win["ref"][j], err)
+        else:
+            B.dg_project(mesh, m_lo, q, tmp)
+            B.dg_error_inf(m_lo, tmp, win["ref"][j], err)
+        errs.append(err.cpu().numpy().tolist())
+    e = np.array(errs)
+    times = win["t0"] + dT * np.arange(n_eval + 1)
+    inwin = (times > win["t0"]) & (times <= win["t0"] + window + 1e-9)
+    beyond = times > win["t0"] + window + 1e-9
+    span = dT * n_eval
+    return {"P": mesh.P, "mode": mode if model is not None else None, "dt": dt, "steps": n * n_eval,
+            "wall_s": wall, "wall_per_unit_time_s": wall / span,
+            "dof_updates_per_s": mesh.E * mesh.n_p * 3 * n * n_eval / wall,
+            "e_max_momentum": e.max(axis=1).tolist(), "times": times.tolist(),
+            "mean_e_window": float(e[inwin].max(axis=1).mean()),
+            "mean_e_beyond": float(e[beyond].max(axis=1).mean()) if beyond.any() else None,
+            "final_e": float(e[-1].max())}
+
+
+def _gain(base, run):
+    e0, e1 = np.array(base["e_max_momentum"]), np.array(run["e_max_momentum"])
+    worse = np.nonzero(e1[1:] > e0[1:])[0]
+    return {"window_ratio": run["mean_e_window"] / base["mean_e_window"],
+            "beyond_ratio": (run["mean_e_beyond"] / base["mean_e_beyond"]) if base["mean_e_beyond"] else None,
+            "better_than_uncorrected_until": base["times"][1 + worse[0]] if len(worse) else base["times"][-1]}
+
+
 def run_study(N=16, Re=1600.0, t0=4.0, window=1.0, snapshots=50, eval_end=5.5, epochs=30, batch=4096,
-              lr=1e-3, seed=0, orders=(4, 5, 6), cfl=0.4, log=print, variants=None):
-    """variants: list of ``variant(...)`` dicts (or (name, mask, epochs, lr)
-    tuples: Eq. (5) pairs, all variables, tanh, every stage); default one
-    such variant from the arguments."""
+              lr=1e-3, seed=0, orders=(4, 5, 6), cfl=0.4, log=print, variants=None, P_lo=3):
+    """One time frame.  variants: list of ``variant(...)`` dicts (or (name,
+    mask, epochs, lr) tuples: Eq. (5) pairs, all variables, tanh, every
+    stage); default one such variant from the arguments."""
     if variants is None:
         variants = [variant("nn", epochs=epochs, lr=lr)]
     variants = [v if isinstance(v, dict) else variant(v[0], mask=v[1], epochs=v[2], lr=v[3]) for v in variants]
     targets = sorted({v["target"] for v in variants})
-    import synthetic
-    out = {"config": dict(N=N, Re=Re, t0=t0, window=window, snapshots=snapshots, eval_end=eval_end,
+    out = {"config": dict(N=N, Re=Re, t0=t0, window=window, snapshots=snapshots, eval_end=eval_end, P_lo=P_lo,
                           batch=batch, seed=seed, orders=list(orders), variants=variants)}
     dT = window / snapshots
     n_eval = int(round((eval_end - t0) / dT))
+    lo = f"P{P_lo}"
 
-    # ---------------------------------------------------------------- step 1
-    m8, m3 = B.Mesh(N, 8, Re), B.Mesh(N, 3, Re)
-    q8 = m8.field()
-    B.dg_init_tgv(m8, q8)
-    # the low-order step inside an interval (Algorithm 1's pairs are per low-order step)
-    q3 = m3.field()
-    B.dg_project(m8, m3, q8, q3)
-    n3 = math.ceil(dT / B.dg_stable_dt(m3, q3, cfl) - 1e-12)
-    dt8_stable = B.dg_stable_dt(m8, q8, cfl)
-    n8 = n3 * math.ceil(dT / n3 / dt8_stable - 1e-12)
-    dt8 = dT / n8
-    k8 = m8.field(0.0)
-    E, np3 = m3.E, m3.n_p
-    data = {}
-    for tg in targets:
-        rows = snapshots * E * (n3 if tg == "alg1" else 1)
-        data[tg] = (torch.empty((rows, 5 * np3), dtype=torch.float32, device="cuda"),
-                    torch.empty((rows, 5 * np3), dtype=torch.float32, device="cuda"))
-    ref3 = torch.empty((n_eval + 1, 5, E, np3), dtype=torch.float64, device="cuda")
-    init = {}
-    ws_eq5 = ws_alg1 = None
-    _sync()
-    t_start = time.perf_counter()
-    B.dg_rk_step(m8, q8, k8, dt8, int(round(t0 / dT)) * n8)
-    _sync()
-    t_ref = time.perf_counter() - t_start
-    log(f"P8 reached t0={t0} in {t_ref:.2f}s ({int(round(t0 / dT)) * n8} steps, dt={dt8:.4e})")
-    meshes = {P: B.Mesh(N, P, Re) for P in orders}
-    for P, m in meshes.items():
-        f = m.field()
-        B.dg_project(m8, m, q8, f)
-        init[P] = f
-    B.dg_project(m8, m3, q8, ref3[0])
-    t_gen = 0.0
-    for j in range(1, n_eval + 1):
-        ta = time.perf_counter()
-        if j <= snapshots and "alg1" in data:
-            X, Y = data["alg1"]
-            for i in range(n3):
-                r0 = ((j - 1) * n3 + i) * E
-                ws_alg1 = B.dg_increment_target(m8, m3, q8, k8, dT / n3, n8 // n3, X[r0:r0 + E], Y[r0:r0 + E],
-                                                 ws=ws_alg1)
-        else:
-            B.dg_rk_step(m8, q8, k8, dt8, n8)
-        B.dg_project(m8, m3, q8, ref3[j])
-        if j <= snapshots and "eq5" in data:
-            X, Y = data["eq5"]
-            ws_eq5 = B.dg_forcing_target(m8, m3, q8, X[(j - 1) * E:j * E], Y[(j - 1) * E:j * E], ws=ws_eq5)
-        _sync()
-        t_gen += time.perf_counter() - ta
-    steps8 = n8 * n_eval
-    out["reference"] = {"P": 8, "dt": dt8, "steps_to_t0": int(round(t0 / dT)) * n8, "seconds_to_t0": t_ref,
-                        "seconds_window_and_eval": t_gen, "steps_window_and_eval": steps8,
-                        "wall_per_unit_time_s": t_gen / (eval_end - t0), "low_order_steps_per_snapshot": n3}
-    log(f"P8 window + evaluation span: {t_gen:.2f}s, datasets " +
-        ", ".join(f"{k} {tuple(v[0].shape)}" for k, v in data.items()))
+    ref = Reference(N, Re, dT, P_lo, cfl)
+    ref.advance_to(t0)
+    t_ref = ref.seconds
+    log(f"P{P_HO} reached t0={t0} in {t_ref:.2f}s (dt={ref.dt_hi:.4e})")
+    win = ref.window(snapshots, n_eval, targets, orders, log)
+    out["reference"] = {"P": P_HO, "dt": ref.dt_hi, "seconds_to_t0": t_ref, "seconds_window_and_eval": win["seconds"],
+                        "wall_per_unit_time_s": win["seconds"] / (eval_end - t0),
+                        "low_order_steps_per_snapshot": ref.n_lo}
 
-    # ---------------------------------------------------------------- step 2
-    norms = {tg: B.nn_data_stats(X, Y, np3) for tg, (X, Y) in data.items()}
+    n_p = ref.m_lo.n_p
+    norms = {tg: B.nn_data_stats(X, Y, n_p) for tg, (X, Y) in win["data"].items()}
     models = {}
     out["training"] = {"norm": norms, "variants": {}}
     for v in variants:
-        X, Y = data[v["target"]]
-        rows = X.shape[0]
-        nb = rows // batch
-        io = MOMENTUM if v["io"] == "momentum" else ALL
-        dims = [len(io) * np3] + HIDDEN + [len(io) * np3]
-        flops = 3 * 2 * sum(a * b for a, b in zip(dims[:-1], dims[1:])) * batch
-        layers = synthetic.mlp_init(dims, seed=seed)
-        model = B.Model(dims, B.pack_params(layers), norms[v["target"]], mask=v["mask"], activation=v["act"],
-                        in_vars=io, out_vars=io)
-        rng = np.random.default_rng(seed)
-        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-        losses = []
-        _sync()
-        ta = time.perf_counter()
-        for ep in range(v["epochs"]):
-            perm = torch.from_numpy(synthetic.epoch_permutation(rows, rng).astype(np.int32)).cuda()
-            ep_loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-            for b in range(nb):
-                B.nn_train_step(model, X, Y, lr=v["lr"], loss=loss, idx=perm[b * batch:(b + 1) * batch])
-                ep_loss += loss
-            losses.append(float(ep_loss.item()) / nb)
-        _sync()
-        t_train = time.perf_counter() - ta
+        X, Y = win["data"][v["target"]]
+        model, _, rec = train(X, Y, n_p, v, batch, seed, norm=norms[v["target"]], log=log)
         models[v["name"]] = (model, v["mode"])
-        out["training"]["variants"][v["name"]] = {
-            **v, "pairs": rows, "batches_per_epoch": nb, "dims": dims, "seconds": t_train,
-            "steps_per_s": v["epochs"] * nb / t_train, "tflops": v["epochs"] * nb * flops / t_train / 1e12,
-            "loss_per_epoch": losses}
-        log(f"training {v['name']} ({v['target']} pairs, {v['io']}, {v['act']}, {v['mode']}): {v['epochs']} epochs "
-            f"x {nb} batches in {t_train:.2f}s, loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+        out["training"]["variants"][v["name"]] = rec
 
-    # ---------------------------------------------------------------- step 3
-    tmp3 = m3.field()
-    err = torch.empty(3, dtype=torch.float64, device="cuda")
-
-    def evolve(mesh, q0, model=None, mode="stage"):
-        q = q0.clone()
-        k = mesh.field(0.0)
-        n = n3 if mesh.P == 3 else math.ceil(dT / B.dg_stable_dt(mesh, q, cfl) - 1e-12)
-        dt = dT / n
-        step = B.dg_rk_step_post if mode == "post" else B.dg_rk_step
-        errs = []
-        wall = 0.0
-        for j in range(n_eval + 1):
-            if j > 0:
-                _sync()
-                ta = time.perf_counter()
-                step(mesh, q, k, dt, n, model=model)
-                _sync()
-                wall += time.perf_counter() - ta
-            if mesh.P == 3:
-                B.dg_error_inf(mesh, q, ref3[j], err)
-            else:
-                B.dg_project(mesh, m3, q, tmp3)
-                B.dg_error_inf(m3, tmp3, ref3[j], err)
-            errs.append(err.cpu().numpy().tolist())
-        e = np.array(errs)
-        times = t0 + dT * np.arange(n_eval + 1)
-        win = (times > t0) & (times <= t0 + window + 1e-9)
-        beyond = times > t0 + window + 1e-9
-        return {"P": mesh.P, "mode": mode if model is not None else None, "dt": dt, "steps": n * n_eval,
-                "wall_s": wall, "wall_per_unit_time_s": wall / (eval_end - t0),
-                "dof_updates_per_s": mesh.E * mesh.n_p * 3 * n * n_eval / wall,
-                "e_max_momentum": e.max(axis=1).tolist(), "times": times.tolist(),
-                "mean_e_window": float(e[win].max(axis=1).mean()),
-                "mean_e_beyond": float(e[beyond].max(axis=1).mean()) if beyond.any() else None,
-                "final_e": float(e[-1].max())}
-
-    runs = {}
-    runs["P3"] = evolve(m3, ref3[0])
+    runs = {lo: evolve(ref, win, ref.m_lo, win["ref"][0], window, cfl=cfl)}
     for name, (model, mode) in models.items():
-        runs[f"P3+{name}"] = evolve(m3, ref3[0], model, mode)
-    for P in orders:
-        runs[f"P{P}"] = evolve(meshes[P], init[P])
+        runs[f"{lo}+{name}"] = evolve(ref, win, ref.m_lo, win["ref"][0], window, model, mode, cfl)
+    for P, (m, f) in win["init"].items():
+        runs[f"P{P}"] = evolve(ref, win, m, f, window, cfl=cfl)
     out["runs"] = runs
     for name, r in runs.items():
         log(f"{name:8s} dt={r['dt']:.3e} wall/unit time={r['wall_per_unit_time_s']:.3f}s "
             f"mean e window={r['mean_e_window']:.3e} beyond={r['mean_e_beyond']} final={r['final_e']:.3e}")
-    p3 = runs["P3"]
     out["gain"], out["comparison"] = {}, {}
     for name in models:
-        p3nn = runs[f"P3+{name}"]
-        e3, en = np.array(p3["e_max_momentum"]), np.array(p3nn["e_max_momentum"])
-        worse = np.nonzero(en[1:] > e3[1:])[0]
-        out["gain"][name] = {"window_ratio": p3nn["mean_e_window"] / p3["mean_e_window"],
-                             "beyond_ratio": (p3nn["mean_e_beyond"] / p3["mean_e_beyond"]) if p3["mean_e_beyond"] else None,
-                             "better_than_p3_until": p3["times"][1 + worse[0]] if len(worse) else p3["times"][-1]}
-        cmp = {}
-        for P in orders:
-            r = runs[f"P{P}"]
-            cmp[f"P{P}"] = {"wall_ratio_vs_p3nn": r["wall_s"] / p3nn["wall_s"],
-                            "error_ratio_p3nn_vs_window": p3nn["mean_e_window"] / r["mean_e_window"],
-                            "error_ratio_p3nn_vs": p3nn["mean_e_beyond"] / r["mean_e_beyond"] if r["mean_e_beyond"] else None}
-        out["comparison"][name] = cmp
+        r = runs[f"{lo}+{name}"]
+        out["gain"][name] = _gain(runs[lo], r)
+        out["comparison"][name] = {
+            f"P{P}": {"wall_ratio_vs_corrected": runs[f"P{P}"]["wall_s"] / r["wall_s"],
+                      "error_ratio_corrected_vs_window": r["mean_e_window"] / runs[f"P{P}"]["mean_e_window"],
+                      "error_ratio_corrected_vs_beyond": (r["mean_e_beyond"] / runs[f"P{P}"]["mean_e_beyond"])
+                      if runs[f"P{P}"]["mean_e_beyond"] else None}
+            for P in win["init"]}
+    return out
+
+
+def run_transfer(N=8, P_lo=3, source=(1600.0, 4.0), target=(1600.0, 7.0), window=0.15, snapshots=100,
+                 eval_span=0.3, net=None, retrain_epochs=50, batch=512, seed=0, cfl=0.4, log=print):
+    """Transfer learning (Sec. 3.5): a network trained on the source frame
+    (Re, t0) is applied to the target frame (Re, t0) as it is ("source"),
+    after `retrain_epochs` epochs of retraining on the target pairs starting
+    from its weights and keeping its normalisation ("retrained"), and
+    compared with a network trained on the target pairs from a Gaussian
+    initialisation for the full epoch count ("scratch") and with the
+    uncorrected low order."""
+    net = net or variant("alg1a", "alg1", "all", "tanh", "post", epochs=200)
+    dT = window / snapshots
+    n_eval = int(round(eval_span / dT))
+    lo = f"P{P_lo}"
+    out = {"config": dict(N=N, P_lo=P_lo, source=list(source), target=list(target), window=window,
+                          snapshots=snapshots, eval_span=eval_span, net=net, retrain_epochs=retrain_epochs,
+                          batch=batch, seed=seed)}
+    refs = {}
+
+    def frame(Re, t0):
+        if Re not in refs:
+            refs[Re] = Reference(N, Re, dT, P_lo, cfl)
+        ref = refs[Re]
+        ref.advance_to(t0)
+        return ref, ref.window(snapshots, n_eval, [net["target"]], (), log)
+
+    ref_s, win_s = frame(*source)
+    n_p = ref_s.m_lo.n_p
+    X, Y = win_s["data"][net["target"]]
+    src_model, src_norm, src_rec = train(X, Y, n_p, net, batch, seed, log=log)
+    del win_s
+    ref_t, win_t = frame(*target)
+    X, Y = win_t["data"][net["target"]]
+    scratch, _, scr_rec = train(X, Y, n_p, {**net, "name": "scratch"}, batch, seed, log=log)
+    retrained, _, ret_rec = train(X, Y, n_p, {**net, "name": "retrained", "epochs": retrain_epochs}, batch, seed,
+                                  norm=src_norm, init_params=src_model.params, log=log)
+    out["training"] = {"source": src_rec, "scratch": scr_rec, "retrained": ret_rec}
+    runs = {lo: evolve(ref_t, win_t, ref_t.m_lo, win_t["ref"][0], window, cfl=cfl)}
+    for name, model in (("source", src_model), ("retrained", retrained), ("scratch", scratch)):
+        runs[f"{lo}+{name}"] = evolve(ref_t, win_t, ref_t.m_lo, win_t["ref"][0], window, model, net["mode"], cfl)
+    out["runs"] = runs
+    for name, r in runs.items():
+        log(f"{name:14s} mean e window={r['mean_e_window']:.3e} beyond={r['mean_e_beyond']} final={r['final_e']:.3e}")
+    out["gain"] = {name: _gain(runs[lo], runs[f"{lo}+{name}"]) for name in ("source", "retrained", "scratch")}
+    out["training_seconds"] = {"scratch": scr_rec["seconds"], "retrained": ret_rec["seconds"]}
+    return out
+
+
+def _variants(spec):
+    out = []
+    for item in spec.split(";"):
+        name, target, io, act, mode, ep, lr = item.split(":")
+        out.append(variant(name, target, io, act, mode, int(ep), float(lr)))
     return out
 
 
@@ -228,6 +348,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--N", type=int, default=16)
     ap.add_argument("--Re", type=float, default=1600.0)
+    ap.add_argument("--P-lo", type=int, default=3)
     ap.add_argument("--t0", type=float, default=4.0)
     ap.add_argument("--window", type=float, default=1.0)
     ap.add_argument("--snapshots", type=int, default=50)
@@ -240,21 +361,28 @@ def main():
     ap.add_argument("--variants", default=None,
                     help="semicolon list name:target:io:act:mode:epochs:lr, e.g. "
                          "nn:eq5:all:tanh:stage:30:1e-3;alg1:alg1:momentum:relu:post:30:1e-3")
+    ap.add_argument("--transfer", default=None,
+                    help="Re_source,t0_source,Re_target,t0_target: transfer-learning run instead of one frame")
+    ap.add_argument("--retrain-epochs", type=int, default=50)
+    ap.add_argument("--eval-span", type=float, default=0.3)
     a = ap.parse_args()
-    variants = None
-    if a.variants:
-        variants = []
-        for item in a.variants.split(";"):
-            name, target, io, act, mode, ep, lr = item.split(":")
-            variants.append(variant(name, target, io, act, mode, int(ep), float(lr)))
     torch.cuda.set_device(0)
-    res = run_study(N=a.N, Re=a.Re, t0=a.t0, window=a.window, snapshots=a.snapshots, eval_end=a.eval_end,
-                    epochs=a.epochs, batch=a.batch, lr=a.lr, orders=tuple(int(x) for x in a.orders.split(",")),
-                    log=lambda *x: print("[study]", *x, flush=True), variants=variants)
-    s = json.dumps(res)
+    log = lambda *x: print("[study]", *x, flush=True)
+    if a.transfer:
+        rs, ts, rt, tt = (float(x) for x in a.transfer.split(","))
+        net = _variants(a.variants)[0] if a.variants else None
+        res = run_transfer(N=a.N, P_lo=a.P_lo, source=(rs, ts), target=(rt, tt), window=a.window,
+                           snapshots=a.snapshots, eval_span=a.eval_span, net=net, retrain_epochs=a.retrain_epochs,
+                           batch=a.batch, log=log)
+        summary = {"gain": res["gain"], "training_seconds": res["training_seconds"]}
+    else:
+        res = run_study(N=a.N, Re=a.Re, t0=a.t0, window=a.window, snapshots=a.snapshots, eval_end=a.eval_end,
+                        epochs=a.epochs, batch=a.batch, lr=a.lr, orders=tuple(int(x) for x in a.orders.split(",")),
+                        log=log, variants=_variants(a.variants) if a.variants else None, P_lo=a.P_lo)
+        summary = {"gain": res["gain"], "comparison": res["comparison"]}
     if a.out:
-        open(a.out, "w").write(s)
-    print(json.dumps({"gain": res["gain"], "comparison": res["comparison"]}))
+        open(a.out, "w").write(json.dumps(res))
+    print(json.dumps(summary))
 
 
 if __name__ == "__main__":

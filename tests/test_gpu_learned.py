@@ -77,6 +77,6 @@ def test_algorithm1_forcing_gains(study):
         a1["wall_per_unit_time_s"], a1a["wall_per_unit_time_s"], p6["wall_per_unit_time_s"]))
     assert a1["mean_e_window"] < 0.5 * p3["mean_e_window"]
     assert a1["mean_e_beyond"] < 0.8 * p3["mean_e_beyond"]
-    assert study["gain"]["alg1"]["better_than_p3_until"] >= 4.3
+    assert study["gain"]["alg1"]["better_than_uncorrected_until"] >= 4.3
     assert a1a["mean_e_window"] <= p6["mean_e_window"]
     assert a1a["wall_s"] < p6["wall_s"] and a1["wall_s"] < p6["wall_s"]
