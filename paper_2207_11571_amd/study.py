@@ -336,6 +336,98 @@ def run_transfer(N=8, P_lo=3, source=(1600.0, 4.0), target=(1600.0, 7.0), window
     return out
 
 
+def run_online(N=8, Re=200.0, P_lo=3, t0=4.0, t_end=7.0, window=0.15, snapshots=100, retrain_window=0.075,
+               retrain_snapshots=50, tol=1e-2, max_retrains=50, net=None, retrain_epochs=50, batch=512, seed=0,
+               cfl=0.4, log=print):
+    """The online retraining loop the paper proposes as future work (Sec. 4):
+    a P = 8 shadow run supplies the error judge; the corrected low-order run
+    starts from the filtered P = 8 state at the end of the first training
+    window, and whenever its error e_n exceeds `tol`, the shadow's next
+    `retrain_window` produces fresh pairs, the network is retrained from its
+    current weights for `retrain_epochs` epochs, and the low-order state is
+    set to the filtered P = 8 state again (Algorithm 1's matching step).
+    Compared, from the same start, with: the first network never retrained
+    but re-matched at the same times ("rematched"), the first network alone
+    ("fixed"), and the uncorrected low order."""
+    net = net or variant("alg1a", "alg1", "all", "tanh", "post", epochs=200)
+    dT = window / snapshots
+    ref = Reference(N, Re, dT, P_lo, cfl)
+    ref.advance_to(t0)
+    win = ref.window(snapshots, snapshots, [net["target"]], (), log)
+    n_p = ref.m_lo.n_p
+    X, Y = win["data"][net["target"]]
+    model, norm, rec0 = train(X, Y, n_p, net, batch, seed, log=log)
+    fixed = model          # retraining builds new models from copies of the weights
+    del win
+    m_lo = ref.m_lo
+    step = B.dg_rk_step_post if net["mode"] == "post" else B.dg_rk_step
+    dt = dT / ref.n_lo
+    names = ("online", "rematched", "fixed", "uncorrected")
+    q = {nm: m_lo.field() for nm in names}
+    B.dg_project(ref.m_hi, m_lo, ref.q, q["online"])
+    for nm in names[1:]:
+        q[nm].copy_(q["online"])
+    k = m_lo.field(0.0)
+    g = m_lo.field()
+    err = torch.empty(3, dtype=torch.float64, device="cuda")
+
+    def advance(nm, n):
+        mdl = {"online": model, "rematched": fixed, "fixed": fixed, "uncorrected": None}[nm]
+        if mdl is None:
+            B.dg_rk_step(m_lo, q[nm], k, dt, n)
+        else:
+            step(m_lo, q[nm], k, dt, n, model=mdl)
+
+    hist = {"t": [], **{nm: [] for nm in names}}
+    events = []
+    seconds = {"low_order": 0.0, "reference": 0.0, "retraining": 0.0}
+    t_ho = 0.0
+    while ref.t < t_end - 1e-9:
+        _sync()
+        ta = time.perf_counter()
+        advance("online", ref.n_lo)
+        _sync()
+        seconds["low_order"] += time.perf_counter() - ta
+        for nm in names[1:]:
+            advance(nm, ref.n_lo)
+        s0 = ref.seconds
+        ref.advance_to(ref.t + dT)
+        seconds["reference"] += ref.seconds - s0
+        B.dg_project(ref.m_hi, m_lo, ref.q, g)
+        hist["t"].append(ref.t)
+        for nm in names:
+            B.dg_error_inf(m_lo, q[nm], g, err)
+            hist[nm].append(float(err.max().item()))
+        e_on = hist["online"][-1]
+        if e_on > tol and len(events) < max_retrains and ref.t + retrain_window < t_end:
+            s0 = ref.seconds
+            w = ref.window(retrain_snapshots, retrain_snapshots, [net["target"]], (), log)
+            seconds["reference"] += ref.seconds - s0
+            t_ho += retrain_window
+            X, Y = w["data"][net["target"]]
+            model, _, rec = train(X, Y, n_p, {**net, "name": "online", "epochs": retrain_epochs}, batch, seed,
+                                  norm=norm, init_params=model.params, log=log)
+            seconds["retraining"] += rec["seconds"]
+            del w
+            B.dg_project(ref.m_hi, m_lo, ref.q, q["online"])
+            q["rematched"].copy_(q["online"])
+            for nm in ("fixed", "uncorrected"):     # they cross the high-order window unchanged in kind
+                advance(nm, ref.n_lo * retrain_snapshots)
+            events.append({"t": ref.t, "e_before": e_on, "train_s": rec["seconds"]})
+            log(f"retrained at t={ref.t:.4f} (e_n {e_on:.3e} > {tol:g})")
+    arr = {nm: np.array(hist[nm]) for nm in names}
+    out = {"config": dict(N=N, Re=Re, P_lo=P_lo, t0=t0, t_end=t_end, window=window, snapshots=snapshots,
+                          retrain_window=retrain_window, tol=tol, retrain_epochs=retrain_epochs, net=net),
+           "history": hist, "retrains": events, "seconds": seconds, "initial_training_s": rec0["seconds"],
+           "high_order_fraction_of_span": t_ho / (t_end - t0 - window),
+           "mean_e": {nm: float(arr[nm].mean()) for nm in names},
+           "max_e": {nm: float(arr[nm].max()) for nm in names},
+           "final_e": {nm: float(arr[nm][-1]) for nm in names}}
+    log(f"online loop to t={ref.t:.3f}: {len(events)} retrains; mean e_n " +
+        ", ".join(f"{nm} {out['mean_e'][nm]:.3e}" for nm in names))
+    return out
+
+
 def _variants(spec):
     out = []
     for item in spec.split(";"):
@@ -364,11 +456,20 @@ def main():
     ap.add_argument("--transfer", default=None,
                     help="Re_source,t0_source,Re_target,t0_target: transfer-learning run instead of one frame")
     ap.add_argument("--retrain-epochs", type=int, default=50)
+    ap.add_argument("--online", default=None, help="t0,t_end: online retraining loop instead of one frame")
+    ap.add_argument("--tol", type=float, default=1e-2)
     ap.add_argument("--eval-span", type=float, default=0.3)
     a = ap.parse_args()
     torch.cuda.set_device(0)
     log = lambda *x: print("[study]", *x, flush=True)
-    if a.transfer:
+    if a.online:
+        t0, t_end = (float(x) for x in a.online.split(","))
+        net = _variants(a.variants)[0] if a.variants else None
+        res = run_online(N=a.N, Re=a.Re, P_lo=a.P_lo, t0=t0, t_end=t_end, window=a.window, snapshots=a.snapshots,
+                         tol=a.tol, net=net, retrain_epochs=a.retrain_epochs, batch=a.batch, log=log)
+        summary = {k: res[k] for k in ("mean_e", "max_e", "final_e", "retrains", "seconds",
+                                       "high_order_fraction_of_span")}
+    elif a.transfer:
         rs, ts, rt, tt = (float(x) for x in a.transfer.split(","))
         net = _variants(a.variants)[0] if a.variants else None
         res = run_transfer(N=a.N, P_lo=a.P_lo, source=(rs, ts), target=(rt, tt), window=a.window,

@@ -44,3 +44,27 @@ def test_retraining_reaches_scratch_accuracy_faster(transfer):
     assert ret["mean_e_window"] < 3.0 * scr["mean_e_window"]
     assert ret["mean_e_beyond"] < 0.5 * p3["mean_e_beyond"]
     assert transfer["training_seconds"]["retrained"] < 0.4 * transfer["training_seconds"]["scratch"]
+
+
+def test_online_retraining_loop():
+    """The retraining loop of the paper's outlook: a P = 8 shadow run judges
+    the corrected P = 3 run at Re 200 from t = 4 to 7; whenever e_n exceeds
+    the tolerance the network is retrained from its current weights on a
+    fresh 0.075-long window and the low order is re-matched to the filtered
+    P = 8 state.  Retraining must beat re-matching alone, the first network
+    alone and the uncorrected low order, and keep e_n near the tolerance."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_11571_amd import study as st
+    say("online retraining loop")
+    tol = 3e-2
+    res = st.run_online(N=8, Re=200.0, P_lo=3, t0=4.0, t_end=7.0, window=0.15, snapshots=100, tol=tol,
+                        retrain_epochs=50, batch=512, log=lambda *a: print("[study]", *a, flush=True))
+    m = res["mean_e"]
+    print("mean e_n: online %.3e rematched %.3e fixed %.3e uncorrected %.3e; %d retrains, high order on %.0f %% "
+          "of the span" % (m["online"], m["rematched"], m["fixed"], m["uncorrected"], len(res["retrains"]),
+                           100 * res["high_order_fraction_of_span"]))
+    assert len(res["retrains"]) >= 1
+    assert m["online"] < 0.25 * m["rematched"]
+    assert m["online"] < 0.1 * m["uncorrected"]
+    assert res["max_e"]["online"] < 2 * tol
