@@ -49,27 +49,28 @@ def parse():
     return ap.parse_args()
 
 
-def time_steps(B, torch, mesh, q, k, dt, steps, model=None):
+def time_steps(B, torch, mesh, q, k, dt, steps, model=None, post=False):
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    step = B.dg_rk_step_post if post else B.dg_rk_step
     t0 = time.perf_counter()
     start.record()
-    B.dg_rk_step(mesh, q, k, dt, steps, model=model)
+    step(mesh, q, k, dt, steps, model=model)
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return wall, start.elapsed_time(stop) / 1e3
 
 
-def solve_case(B, torch, N, P, Re, Cs, steps, warmup, model=None):
+def solve_case(B, torch, N, P, Re, Cs, steps, warmup, model=None, post=False):
     mesh = B.Mesh(N, P, Re, Cs=Cs)
     q = mesh.field()
     B.dg_init_tgv(mesh, q)
     dt = B.dg_stable_dt(mesh, q)
     k = mesh.field(0.0)
     if warmup:
-        B.dg_rk_step(mesh, q, k, dt, warmup, model=model)
-    wall, ev = time_steps(B, torch, mesh, q, k, dt, steps, model)
+        (B.dg_rk_step_post if post else B.dg_rk_step)(mesh, q, k, dt, warmup, model=model)
+    wall, ev = time_steps(B, torch, mesh, q, k, dt, steps, model, post)
     prof = B.dg_profile_steps(mesh, q, k, dt, 5, model=model)
     nodes = mesh.E * mesh.n_p
     rate = nodes * 3 * steps / wall
@@ -79,11 +80,53 @@ def solve_case(B, torch, N, P, Re, Cs, steps, warmup, model=None):
             "kernel_ms": prof, "ke_end": float(d[0]), "finite": bool(math.isfinite(d[0]))}
 
 
-def net_model(B, synthetic):
+NET_NORM = [1.0, 0.0, 0.0, 0.0, None, 0.01, 1, 1, 1, 1, 0, 0, 0, 0, 0, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3]
+
+
+def net_model(B, synthetic, momentum=False, train=False):
+    """The Gaussian-initialised forcing network: 320-256-256-256-320 tanh on
+    all five variables, or (momentum=True) the paper's form, 192-256-256-256-192
+    relu on the three momenta."""
+    norm = list(NET_NORM)
+    norm[4] = synthetic.TGV_ENERGY_LEVEL
+    if momentum:
+        dims = [192, 256, 256, 256, 192]
+        return B.Model(dims, B.pack_params(synthetic.mlp_init(dims, seed=0)), norm, activation="relu", train=train,
+                       in_vars=(1, 2, 3), out_vars=(1, 2, 3))
     dims = [320, 256, 256, 256, 320]
-    norm = [1.0, 0.0, 0.0, 0.0, synthetic.TGV_ENERGY_LEVEL, 0.01, 1, 1, 1, 1,
-            0, 0, 0, 0, 0, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3]
-    return B.Model(dims, B.pack_params(synthetic.mlp_init(dims, seed=0)), norm, train=False)
+    return B.Model(dims, B.pack_params(synthetic.mlp_init(dims, seed=0)), norm, train=train)
+
+
+def train_case(B, torch, synthetic, batch, steps, warmup):
+    """Adam steps of the 320-256-256-256-320 network on batches of `batch`
+    rows drawn from a 16-batch synthetic dataset of TGV-magnitude rows."""
+    import numpy as np
+    rows = 16 * batch
+    x = synthetic.random_rows(rows, 320, seed=5)
+    x[:, :64] = 1.0 + 0.01 * x[:, :64]
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL + x[:, 256:]
+    y = synthetic.random_rows(rows, 320, seed=6, scale=1e-3)
+    X, Y = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    model = net_model(B, synthetic, train=True)
+    idx = torch.from_numpy(np.random.default_rng(0).permutation(rows).astype(np.int32)).cuda()
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def run(n, first):
+        for i in range(n):
+            j = (first + i) % 16
+            B.nn_train_step(model, X, Y, lr=1e-3, loss=loss, idx=idx[j * batch:(j + 1) * batch])
+
+    run(warmup, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps, warmup)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dims = [320, 256, 256, 256, 320]
+    flop = 3 * 2 * sum(a * b for a, b in zip(dims[:-1], dims[1:])) * batch
+    return {"batch": batch, "steps": steps, "ms_per_step": 1e3 * wall / steps, "steps_per_s": steps / wall,
+            "tflops": flop * steps / wall / 1e12, "gflop_per_step": flop / 1e9,
+            "workload": "Adam step, 320-256-256-256-320 tanh, bf16 matrix cores, float32 master weights"}
 
 
 def percentile(xs, p):
@@ -220,6 +263,11 @@ def main():
     model = net_model(B, synthetic)
     p3nn = solve_case(B, torch, 16, 3, 200.0, 0.0, args.steps, args.warmup, model=model)
     p3 = solve_case(B, torch, 16, 3, 200.0, 0.0, args.steps, args.warmup)
+    log("P3 + paper-form network after each step (Algorithm 1)")
+    p3post = solve_case(B, torch, 16, 3, 200.0, 0.0, args.steps, args.warmup,
+                        model=net_model(B, synthetic, momentum=True), post=True)
+    log("training step, batch 4096")
+    training = train_case(B, torch, synthetic, 4096, 50, 5)
 
     resid_ms = head["kernel_ms"]["resid"]
     achieved = ALG_BYTES_RESID * head["nodes"] / (resid_ms * 1e-3) / 1e9
@@ -292,6 +340,10 @@ def main():
                   "network_share_of_stage": p3nn["kernel_ms"]["net"] / max(1e-12, sum(p3nn["kernel_ms"][k] for k in ("grad", "net", "resid"))),
                   "workload": "corrected P=3, 16^3, Re 200, 320-256-256-256-320 tanh bf16 network every stage"},
         "p3_plain": {"dof_updates_per_s": p3["dof_updates_per_s"], "ms_per_step": p3["ms_per_step"]},
+        "p3_nn_post": {"dof_updates_per_s": p3post["dof_updates_per_s"], "ms_per_step": p3post["ms_per_step"],
+                       "workload": "P=3, 16^3, Re 200, 192-256-256-256-192 relu network on the momenta, "
+                                   "correction after each step (Algorithm 1)"},
+        "training": training,
         "p8": {"dof_updates_per_s": p8["dof_updates_per_s"], "ms_per_step": p8["ms_per_step"],
                "kernel_ms": p8["kernel_ms"],
                "resid_hbm_alg_GBs": ALG_BYTES_RESID * p8["nodes"] / (p8["kernel_ms"]["resid"] * 1e-3) / 1e9},
