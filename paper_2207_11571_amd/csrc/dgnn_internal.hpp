@@ -153,17 +153,40 @@ struct TrainArgs {
     float grad_scale;                 // 2 / (B * dims[L])
     uint16_t* actT[kMaxLayers];       // [pdims[l]][Bp]  (act[0] = xhat)
     uint16_t* dzT[kMaxLayers];        // [pdims[l+1]][Bp]
+    float* bias_part[kMaxLayers];     // [Bp / 16][pdims[l+1]] row-block sums of dz_l
     float* loss_part;                 // [Bp / 16]
+};
+
+// All layers' weight and bias gradients of one training step: split-K
+// partial products, then one fixed-order reduction.
+struct GradArgs {
+    const uint16_t* dzT[kMaxLayers];
+    const uint16_t* actT[kMaxLayers];
+    float* part[kMaxLayers];          // [nks][pout][pin]
+    const float* bias_part[kMaxLayers];
+    float* gW[kMaxLayers];
+    float* gb[kMaxLayers];
+    int pout[kMaxLayers], pin[kMaxLayers], dout[kMaxLayers], din[kMaxLayers];
+    int tblk[kMaxLayers + 1];         // product blocks before layer l (four 16x16 tiles each)
+    int rblk[kMaxLayers + 1];         // reduction blocks before layer l (256 outputs each)
+    int n_layers, Bp, kchunk, nks, nrb;
+};
+
+// Adam on the float32 master weights with the bf16 copies W_l, W_l^T written
+// in the same pass.
+struct ParamMap {
+    int64_t woff[kMaxLayers], boff[kMaxLayers], wbo[kMaxLayers], wtbo[kMaxLayers];
+    int din[kMaxLayers], dout[kMaxLayers], pin[kMaxLayers], pout[kMaxLayers];
+    int n_layers;
 };
 size_t train_smem_bytes(const NetArgs& na);
 hipError_t launch_train_rows(const NetArgs& na, const TrainArgs& ta, int nblocks, hipStream_t st);
-hipError_t launch_wgrad(const uint16_t* dzT, const uint16_t* actT, int Bp, int pout, int pin, int dout, int din,
-                        int nks, float* part, float* gW, float* gb, hipStream_t st);
+hipError_t launch_grads(const GradArgs& ga, hipStream_t st);
 hipError_t launch_loss_final(const float* part, int n, float inv_count, float* loss, hipStream_t st);
 hipError_t launch_data_stats(const float* x, const float* y, int64_t rows, int n_p, double* part, int nblocks,
                              double* out_dev, hipStream_t st);
-hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t n,
-                       float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st);
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t n, const ParamMap& pm,
+                       uint16_t* wbf, float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st);
 
 // error reporting (thread-local)
 int set_error(int code, const char* fmt, ...);

@@ -119,8 +119,8 @@ static int refresh(nn_model* m, hipStream_t st) {
 }
 
 struct TrainLayout {
-    size_t actT[kMaxLayers], dzT[kMaxLayers], part, loss, total;
-    int Bp, nks;
+    size_t actT[kMaxLayers], dzT[kMaxLayers], part[kMaxLayers], bpart[kMaxLayers], loss, total;
+    int Bp, nks, nrb;
 };
 
 static TrainLayout train_layout(const nn_model* m, int batch) {
@@ -130,18 +130,18 @@ static TrainLayout train_layout(const nn_model* m, int batch) {
     T.nks = T.Bp / 256;
     if (T.nks < 1) T.nks = 1;
     if (T.nks > 16) T.nks = 16;
+    T.nrb = T.Bp / 16;
     size_t off = 0;
-    size_t maxw = 0;
     for (int l = 0; l < m->n_layers; ++l) {
         T.actT[l] = off;
         off += align256((size_t)m->pdims[l] * T.Bp * sizeof(uint16_t));
         T.dzT[l] = off;
         off += align256((size_t)m->pdims[l + 1] * T.Bp * sizeof(uint16_t));
-        const size_t w = (size_t)m->pdims[l] * m->pdims[l + 1];
-        if (w > maxw) maxw = w;
+        T.part[l] = off;
+        off += align256((size_t)T.nks * m->pdims[l] * m->pdims[l + 1] * sizeof(float));
+        T.bpart[l] = off;
+        off += align256((size_t)T.nrb * m->pdims[l + 1] * sizeof(float));
     }
-    T.part = off;
-    off += align256((size_t)T.nks * maxw * sizeof(float));
     T.loss = off;
     off += align256((size_t)(T.Bp / 16 + 1) * sizeof(float));
     T.total = off;
@@ -293,22 +293,56 @@ int nn_train_step(nn_model* m, const float* x, const float* y, const int32_t* id
     for (int l = 0; l < m->n_layers; ++l) {
         ta.actT[l] = (uint16_t*)(base + T.actT[l]);
         ta.dzT[l] = (uint16_t*)(base + T.dzT[l]);
+        ta.bias_part[l] = (float*)(base + T.bpart[l]);
     }
     ta.loss_part = (float*)(base + T.loss);
-    const int nblocks = T.Bp / 16;
+    const int nblocks = T.nrb;
     NN_HIP(launch_train_rows(na, ta, nblocks, st));
-    for (int l = 0; l < m->n_layers; ++l)
-        NN_HIP(launch_wgrad(ta.dzT[l], ta.actT[l], T.Bp, m->pdims[l + 1], m->pdims[l], m->dims[l + 1], m->dims[l],
-                            T.nks, (float*)(base + T.part), m->grad + m->woff[l], m->grad + m->boff[l], st));
+    GradArgs ga;
+    std::memset(&ga, 0, sizeof(ga));
+    ga.n_layers = m->n_layers;
+    ga.Bp = T.Bp;
+    ga.nks = T.nks;
+    ga.nrb = T.nrb;
+    ga.kchunk = ((T.Bp + T.nks - 1) / T.nks + 31) / 32 * 32;
+    for (int l = 0; l < m->n_layers; ++l) {
+        ga.dzT[l] = ta.dzT[l];
+        ga.actT[l] = ta.actT[l];
+        ga.part[l] = (float*)(base + T.part[l]);
+        ga.bias_part[l] = ta.bias_part[l];
+        ga.gW[l] = m->grad + m->woff[l];
+        ga.gb[l] = m->grad + m->boff[l];
+        ga.pout[l] = m->pdims[l + 1];
+        ga.pin[l] = m->pdims[l];
+        ga.dout[l] = m->dims[l + 1];
+        ga.din[l] = m->dims[l];
+        const int ntiles = (ga.pout[l] / 16) * (ga.pin[l] / 16);
+        ga.tblk[l + 1] = ga.tblk[l] + (ntiles + 3) / 4;
+        ga.rblk[l + 1] = ga.rblk[l] + (ga.dout[l] * ga.din[l] + 255) / 256;
+    }
+    NN_HIP(launch_grads(ga, st));
     if (loss_dev)
         NN_HIP(launch_loss_final(ta.loss_part, nblocks, (float)(1.0 / ((double)batch * m->dims[m->n_layers])),
                                  loss_dev, st));
     m->step += 1;
     const double bc1 = 1.0 - std::pow(0.9, (double)m->step);
     const double bc2 = 1.0 - std::pow(0.999, (double)m->step);
-    NN_HIP(launch_adam(m->params, m->grad, m->adam_m, m->adam_v, m->n_params, lr, 0.9f, 0.999f, 1e-7f, (float)bc1,
-                       (float)bc2, st));
-    return refresh(m, st);
+    ParamMap pm;
+    std::memset(&pm, 0, sizeof(pm));
+    pm.n_layers = m->n_layers;
+    for (int l = 0; l < m->n_layers; ++l) {
+        pm.woff[l] = m->woff[l];
+        pm.boff[l] = m->boff[l];
+        pm.wbo[l] = m->wbf_off[l];
+        pm.wtbo[l] = m->wtbf_off[l];
+        pm.din[l] = m->dims[l];
+        pm.dout[l] = m->dims[l + 1];
+        pm.pin[l] = m->pdims[l];
+        pm.pout[l] = m->pdims[l + 1];
+    }
+    NN_HIP(launch_adam(m->params, m->grad, m->adam_m, m->adam_v, m->n_params, pm, m->wbf, lr, 0.9f, 0.999f, 1e-7f,
+                       (float)bc1, (float)bc2, st));
+    return DG_OK;
 }
 
 size_t nn_stats_ws(int64_t rows) {

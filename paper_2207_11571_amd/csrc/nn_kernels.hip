@@ -285,6 +285,12 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
         __syncthreads();
     }
     if (t == 0) ta.loss_part[blockIdx.x] = red[0];
+    // row-block sums of dz for the bias gradients (g0 is complete after the barriers above)
+    for (int c = t; c < na.pdims[L]; c += kRowThreads) {
+        float sacc = 0.0f;
+        for (int rr = 0; rr < kRows; ++rr) sacc += bf2f(g0[rr * ld + c]);
+        ta.bias_part[L - 1][(size_t)blockIdx.x * na.pdims[L] + c] = sacc;
+    }
     // transposed activations and dz_{L-1}
     for (int l = 0; l < L; ++l) {
         const int pd = na.pdims[l];
@@ -316,6 +322,11 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
             const int c = idx / kRows, r = idx - c * kRows;
             ta.dzT[l - 1][(size_t)c * Bp + r0 + r] = gout[r * ld + c];
         }
+        for (int c = t; c < Np; c += kRowThreads) {
+            float sacc = 0.0f;
+            for (int rr = 0; rr < kRows; ++rr) sacc += bf2f(gout[rr * ld + c]);
+            ta.bias_part[l - 1][(size_t)blockIdx.x * Np + c] = sacc;
+        }
         uint16_t* tmp = gin;
         gin = gout;
         gout = tmp;
@@ -323,61 +334,81 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
     }
 }
 
-// Weight-gradient partials: part[ks][o][i] = sum over the batch slice ks of
-// dzT[o][b] actT[i][b].  Each wave computes one 16 x 16 tile.
-__global__ void __launch_bounds__(kThreads) k_wgrad(const uint16_t* __restrict__ dzT, const uint16_t* __restrict__ actT,
-                                                   int Bp, int pout, int pin, int kchunk, float* __restrict__ part) {
+// Weight-gradient partials of every layer in one launch: part_l[ks][o][i] =
+// sum over the batch slice ks of dzT_l[o][b] actT_l[i][b].  Each wave computes
+// one 16 x 16 tile; block x (four tiles) belongs to the layer whose block
+// range holds it.
+__global__ void __launch_bounds__(kThreads) k_wgrad(GradArgs ga) {
+    int l = 0;
+    while (l + 1 < ga.n_layers && (int)blockIdx.x >= ga.tblk[l + 1]) ++l;
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
+    const int pout = ga.pout[l], pin = ga.pin[l], Bp = ga.Bp;
     const int tiles_i = pin / 16;
-    const int tile = blockIdx.x * 4 + wave;
+    const int tile = ((int)blockIdx.x - ga.tblk[l]) * 4 + wave;
     const int ntiles = (pout / 16) * tiles_i;
     if (tile >= ntiles) return;
     const int to = tile / tiles_i, tii = tile - to * tiles_i;
     const int ks = blockIdx.y;
-    const int kb = ks * kchunk;
-    const int ke = kb + kchunk < Bp ? kb + kchunk : Bp;
+    const int kb = ks * ga.kchunk;
+    const int ke = kb + ga.kchunk < Bp ? kb + ga.kchunk : Bp;
     const int r = lane & 15, kq = 8 * (lane >> 4);
-    const uint16_t* arow = dzT + (size_t)(to * 16 + r) * Bp + kq;
-    const uint16_t* brow = actT + (size_t)(tii * 16 + r) * Bp + kq;
+    const uint16_t* arow = ga.dzT[l] + (size_t)(to * 16 + r) * Bp + kq;
+    const uint16_t* brow = ga.actT[l] + (size_t)(tii * 16 + r) * Bp + kq;
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = kb; k0 < ke; k0 += 32) {
+    // four K slices' fragments in flight before their products
+    int k0 = kb;
+    for (; k0 + 128 <= ke; k0 += 128) {
+        bf16x8 a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = *(const bf16x8*)(arow + k0 + 32 * u);
+            b[u] = *(const bf16x8*)(brow + k0 + 32 * u);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b[u], acc, 0, 0, 0);
+    }
+    for (; k0 < ke; k0 += 32) {
         const bf16x8 a = *(const bf16x8*)(arow + k0);
         const bf16x8 b = *(const bf16x8*)(brow + k0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
     }
-    float* o = part + (size_t)ks * pout * pin;
+    float* o = ga.part[l] + (size_t)ks * pout * pin;
 #pragma unroll
     for (int i = 0; i < 4; ++i) o[(size_t)(to * 16 + 4 * (lane >> 4) + i) * pin + tii * 16 + r] = acc[i];
 }
 
-// grad W_l = sum of the partials (fixed order); grad b_l = row sums of dz_l
-__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ part, int nks, int pout, int pin,
-                                                     int dout, int din, float* __restrict__ gW) {
-    const int total = dout * din;
-    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += gridDim.x * 256) {
+// grad W_l = sum of the split-K partials, every layer in one launch, each
+// sum in a fixed order
+__global__ void __launch_bounds__(256) k_grad_reduce(GradArgs ga) {
+    int l = 0;
+    while (l + 1 < ga.n_layers && (int)blockIdx.x >= ga.rblk[l + 1]) ++l;
+    const int idx = ((int)blockIdx.x - ga.rblk[l]) * 256 + threadIdx.x;
+    const int dout = ga.dout[l], din = ga.din[l], pout = ga.pout[l], pin = ga.pin[l];
+    if (idx < dout * din) {
         const int o = idx / din, i = idx - o * din;
         float s = 0.0f;
-        for (int k = 0; k < nks; ++k) s += part[(size_t)k * pout * pin + (size_t)o * pin + i];
-        gW[idx] = s;
+        for (int k = 0; k < ga.nks; ++k) s += ga.part[l][(size_t)k * pout * pin + (size_t)o * pin + i];
+        ga.gW[l][idx] = s;
     }
 }
 
-__global__ void __launch_bounds__(256) k_bias_grad(const uint16_t* __restrict__ dzT, int Bp, int dout,
-                                                  float* __restrict__ gb) {
-    __shared__ float red[256];
-    const int o = blockIdx.x;
-    const int t = threadIdx.x;
-    float s = 0.0f;
-    if (o < dout)
-        for (int b = t; b < Bp; b += 256) s += bf2f(dzT[(size_t)o * Bp + b]);
-    red[t] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
+// grad b_l = sum of the row-block sums of dz_l: one wavefront per bias
+// entry, lane-strided partial sums, then a fixed butterfly over the lanes
+__global__ void __launch_bounds__(256) k_bias_reduce(GradArgs ga, int nbias) {
+    const int w = (int)blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (w >= nbias) return;
+    int l = 0, o = w;
+    while (l + 1 < ga.n_layers && o >= ga.dout[l]) {
+        o -= ga.dout[l];
+        ++l;
     }
-    if (t == 0 && o < dout) gb[o] = red[0];
+    const int pout = ga.pout[l];
+    float s = 0.0f;
+    for (int k = lane; k < ga.nrb; k += 64) s += ga.bias_part[l][(size_t)k * pout + o];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) ga.gb[l][o] = s;
 }
 
 __global__ void __launch_bounds__(256) k_loss_final(const float* __restrict__ part, int n, float inv_count,
@@ -396,15 +427,26 @@ __global__ void __launch_bounds__(256) k_loss_final(const float* __restrict__ pa
 }
 
 __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                                             float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
-                                             float bc1, float bc2) {
+                                             float* __restrict__ v, int64_t n, ParamMap pm, uint16_t* __restrict__ wbf,
+                                             float lr, float b1, float b2, float eps, float bc1, float bc2) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const float gi = g[i];
         const float mi = b1 * m[i] + (1.0f - b1) * gi;
         const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        p[i] = pi;
+        // weights also go to their bf16 copies W_l [pout][pin] and W_l^T [pin][pout]
+        int l = 0;
+        while (l + 1 < pm.n_layers && i >= pm.woff[l + 1]) ++l;
+        if (i < pm.boff[l]) {
+            const int64_t w = i - pm.woff[l];
+            const int o = (int)(w / pm.din[l]), ii = (int)(w - (int64_t)o * pm.din[l]);
+            const uint16_t h = f2bf(pi);
+            wbf[pm.wbo[l] + (int64_t)o * pm.pin[l] + ii] = h;
+            wbf[pm.wtbo[l] + (int64_t)ii * pm.pout[l] + o] = h;
+        }
     }
 }
 
@@ -552,16 +594,12 @@ hipError_t launch_train_rows(const NetArgs& na, const TrainArgs& ta, int nblocks
     return hipGetLastError();
 }
 
-hipError_t launch_wgrad(const uint16_t* dzT, const uint16_t* actT, int Bp, int pout, int pin, int dout, int din,
-                        int nks, float* part, float* gW, float* gb, hipStream_t st) {
-    const int ntiles = (pout / 16) * (pin / 16);
-    const int kchunk = ((Bp + nks - 1) / nks + 31) / 32 * 32;
-    hipLaunchKernelGGL(k_wgrad, dim3((ntiles + 3) / 4, nks), dim3(kThreads), 0, st, dzT, actT, Bp, pout, pin,
-                       kchunk, part);
-    int blocks = (dout * din + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks), dim3(256), 0, st, part, nks, pout, pin, dout, din, gW);
-    hipLaunchKernelGGL(k_bias_grad, dim3(dout), dim3(256), 0, st, dzT, Bp, dout, gb);
+hipError_t launch_grads(const GradArgs& ga, hipStream_t st) {
+    hipLaunchKernelGGL(k_wgrad, dim3(ga.tblk[ga.n_layers], ga.nks), dim3(kThreads), 0, st, ga);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(ga.rblk[ga.n_layers]), dim3(256), 0, st, ga);
+    int nbias = 0;
+    for (int l = 0; l < ga.n_layers; ++l) nbias += ga.dout[l];
+    hipLaunchKernelGGL(k_bias_reduce, dim3((nbias + 3) / 4), dim3(256), 0, st, ga, nbias);
     return hipGetLastError();
 }
 
@@ -570,11 +608,12 @@ hipError_t launch_loss_final(const float* part, int n, float inv_count, float* l
     return hipGetLastError();
 }
 
-hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t n, float lr, float b1, float b2,
-                       float eps, float bc1, float bc2, hipStream_t st) {
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t n, const ParamMap& pm,
+                       uint16_t* wbf, float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st) {
     int blocks = (int)((n + 255) / 256);
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, st, params, grad, m, v, n, lr, b1, b2, eps, bc1, bc2);
+    hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, st, params, grad, m, v, n, pm, wbf, lr, b1, b2, eps, bc1,
+                       bc2);
     return hipGetLastError();
 }
 
