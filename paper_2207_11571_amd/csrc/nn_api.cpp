@@ -316,7 +316,7 @@ int nn_train_step(nn_model* m, const float* x, const float* y, const int32_t* id
         ga.pin[l] = m->pdims[l];
         ga.dout[l] = m->dims[l + 1];
         ga.din[l] = m->dims[l];
-        const int ntiles = (ga.pout[l] / 16) * (ga.pin[l] / 16);
+        const int ntiles = (ga.pout[l] / 32) * (ga.pin[l] / 32);
         ga.tblk[l + 1] = ga.tblk[l] + (ntiles + 3) / 4;
         ga.rblk[l + 1] = ga.rblk[l] + (ga.dout[l] * ga.din[l] + 255) / 256;
     }

@@ -336,46 +336,51 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
 
 // Weight-gradient partials of every layer in one launch: part_l[ks][o][i] =
 // sum over the batch slice ks of dzT_l[o][b] actT_l[i][b].  Each wave computes
-// one 16 x 16 tile; block x (four tiles) belongs to the layer whose block
-// range holds it.
+// one 32 x 32 tile as 2 x 2 MFMA tiles, so every fragment it loads feeds two
+// products; block x (four tiles) belongs to the layer whose block range
+// holds it.
 __global__ void __launch_bounds__(kThreads) k_wgrad(GradArgs ga) {
     int l = 0;
     while (l + 1 < ga.n_layers && (int)blockIdx.x >= ga.tblk[l + 1]) ++l;
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
     const int pout = ga.pout[l], pin = ga.pin[l], Bp = ga.Bp;
-    const int tiles_i = pin / 16;
+    const int tiles_i = pin / 32;
     const int tile = ((int)blockIdx.x - ga.tblk[l]) * 4 + wave;
-    const int ntiles = (pout / 16) * tiles_i;
+    const int ntiles = (pout / 32) * tiles_i;
     if (tile >= ntiles) return;
     const int to = tile / tiles_i, tii = tile - to * tiles_i;
     const int ks = blockIdx.y;
     const int kb = ks * ga.kchunk;
     const int ke = kb + ga.kchunk < Bp ? kb + ga.kchunk : Bp;
     const int r = lane & 15, kq = 8 * (lane >> 4);
-    const uint16_t* arow = ga.dzT[l] + (size_t)(to * 16 + r) * Bp + kq;
-    const uint16_t* brow = ga.actT[l] + (size_t)(tii * 16 + r) * Bp + kq;
-    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    // four K slices' fragments in flight before their products
-    int k0 = kb;
-    for (; k0 + 128 <= ke; k0 += 128) {
-        bf16x8 a[4], b[4];
+    const uint16_t* arow0 = ga.dzT[l] + (size_t)(to * 32 + r) * Bp + kq;
+    const uint16_t* arow1 = arow0 + (size_t)16 * Bp;
+    const uint16_t* brow0 = ga.actT[l] + (size_t)(tii * 32 + r) * Bp + kq;
+    const uint16_t* brow1 = brow0 + (size_t)16 * Bp;
+    floatx4 acc[2][2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            a[u] = *(const bf16x8*)(arow + k0 + 32 * u);
-            b[u] = *(const bf16x8*)(brow + k0 + 32 * u);
-        }
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b[u], acc, 0, 0, 0);
-    }
-    for (; k0 < ke; k0 += 32) {
-        const bf16x8 a = *(const bf16x8*)(arow + k0);
-        const bf16x8 b = *(const bf16x8*)(brow + k0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+        const bf16x8 a0 = *(const bf16x8*)(arow0 + k0);
+        const bf16x8 a1 = *(const bf16x8*)(arow1 + k0);
+        const bf16x8 b0 = *(const bf16x8*)(brow0 + k0);
+        const bf16x8 b1 = *(const bf16x8*)(brow1 + k0);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
     }
     float* o = ga.part[l] + (size_t)ks * pout * pin;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) o[(size_t)(to * 16 + 4 * (lane >> 4) + i) * pin + tii * 16 + r] = acc[i];
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                o[(size_t)(to * 32 + 16 * i + 4 * (lane >> 4) + v) * pin + tii * 32 + 16 * j + r] = acc[i][j][v];
 }
 
 // grad W_l = sum of the split-K partials, every layer in one launch, each
