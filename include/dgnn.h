@@ -253,7 +253,8 @@ typedef struct solve_request {
     const nn_model* model;
     double* ke_host;                /* host, ke_capacity doubles (t, KE) pairs; may be NULL */
     int32_t ke_capacity;            /* number of (t, KE) pairs ke_host holds       */
-    int32_t reserved;
+    int32_t nn_after_step;          /* use_nn: 0 forcing at every stage (Eq. (4)),
+                                       1 correction after each step (Algorithm 1)  */
     double* q_out_host;             /* host, final state 5 E n_p doubles; may be NULL */
 } solve_request;
 

@@ -38,7 +38,7 @@ class solve_request(ctypes.Structure):
                 ("Cs", ctypes.c_double), ("P", ctypes.c_int32), ("N", ctypes.c_int32),
                 ("use_nn", ctypes.c_int32), ("ke_every", ctypes.c_int32), ("model", ctypes.c_void_p),
                 ("ke_host", ctypes.POINTER(ctypes.c_double)), ("ke_capacity", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("q_out_host", ctypes.POINTER(ctypes.c_double))]
+                ("nn_after_step", ctypes.c_int32), ("q_out_host", ctypes.POINTER(ctypes.c_double))]
 
 
 class solve_status(ctypes.Structure):
@@ -365,7 +365,9 @@ class Server:
         self._keep = {}
 
     def submit(self, Re, P, N, t_end, use_nn=False, model=None, ke_every=1, ke_capacity=0, Cs=0.0, Mach=0.1,
-               want_state=False):
+               want_state=False, after_step=False):
+        """after_step: with use_nn, Algorithm 1's correction after each step
+        instead of the forcing at every stage."""
         import numpy as np
         r = solve_request()
         r.Re, r.t_end, r.Mach, r.Cs = Re, t_end, Mach, Cs
@@ -375,6 +377,7 @@ class Server:
         qout = np.zeros(5 * N ** 3 * (P + 1) ** 3) if want_state else None
         r.ke_host = ke.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if ke_capacity > 0 else None
         r.ke_capacity = ke_capacity
+        r.nn_after_step = 1 if after_step else 0
         r.q_out_host = qout.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_state else None
         rid = ctypes.c_uint64()
         check(lib().solve_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))

@@ -55,7 +55,7 @@ static Foot foot(const Mesh& m) {
     f.k = field;
     f.ws = 2 * field;
     f.desc = f.ws + a256(ws_layout(m).total);
-    f.hist = f.desc + a256(2 * sizeof(SolveDesc));
+    f.hist = f.desc + a256(4 * sizeof(SolveDesc));
     f.total = f.hist + a256(kHist * kDiagDoubles * sizeof(double));
     return f;
 }
@@ -197,21 +197,27 @@ static int admit_one(solve_server* S, Solve* s) {
     if (s->n_steps < 1) s->n_steps = 1;
     s->dt = s->req.t_end / s->n_steps;
     const WsLayout L = ws_layout(s->mesh);
-    SolveDesc d[2];
-    for (int par = 0; par < 2; ++par) {
-        std::memset(&d[par], 0, sizeof(SolveDesc));
-        d[par].q = s->q;
-        d[par].k = s->k;
-        d[par].forcing = s->req.use_nn ? (const double*)(s->ws + L.forcing) : nullptr;
-        d[par].qtr_in = (const double*)(s->ws + (par == 0 ? L.qtr0 : L.qtr1));
-        d[par].qtr_out = (double*)(s->ws + (par == 0 ? L.qtr1 : L.qtr0));
-        d[par].fv = (double*)(s->ws + L.fv);
-        d[par].N = s->mesh.N;
-        d[par].E = s->mesh.E;
-        d[par].dt = s->dt;
-        d[par].ph = s->mesh.ph;
+    // d[par]: the stages; d[2 + par]: the last stage of a step corrected after
+    // the step (Algorithm 1), whose update adds dt s(q^n)
+    const bool post = s->req.use_nn && s->req.nn_after_step;
+    const double* fbuf = s->req.use_nn ? (const double*)(s->ws + L.forcing) : nullptr;
+    SolveDesc d[4];
+    for (int p = 0; p < 4; ++p) {
+        const int par = p & 1;
+        std::memset(&d[p], 0, sizeof(SolveDesc));
+        d[p].q = s->q;
+        d[p].k = s->k;
+        d[p].forcing = post ? nullptr : fbuf;
+        d[p].post = (post && p >= 2) ? fbuf : nullptr;
+        d[p].qtr_in = (const double*)(s->ws + (par == 0 ? L.qtr0 : L.qtr1));
+        d[p].qtr_out = (double*)(s->ws + (par == 0 ? L.qtr1 : L.qtr0));
+        d[p].fv = (double*)(s->ws + L.fv);
+        d[p].N = s->mesh.N;
+        d[p].E = s->mesh.E;
+        d[p].dt = s->dt;
+        d[p].ph = s->mesh.ph;
     }
-    if (launch_write_descs(d, 2, s->ddesc, S->st) != hipSuccess) return set_error(DG_EHIP, "descriptor upload failed");
+    if (launch_write_descs(d, 4, s->ddesc, S->st) != hipSuccess) return set_error(DG_EHIP, "descriptor upload failed");
     if (launch_traces(s->mesh.PP, single_list(s->ddesc + 1, s->mesh.E), S->st) != hipSuccess)
         return set_error(DG_EHIP, "trace launch failed");
     // record KE(0)
@@ -242,7 +248,8 @@ static int step_group(solve_server* S, int PP, std::vector<Solve*>& v, hipStream
             int blk = 0;
             for (size_t i = 0; i < cn; ++i) {
                 Solve* s = v[c0 + i];
-                dl.d[i] = s->ddesc + s->par;
+                const bool post = s->req.use_nn && s->req.nn_after_step;
+                dl.d[i] = s->ddesc + s->par + ((post && stg == 2) ? 2 : 0);
                 dl.blk[i] = blk;
                 blk += s->mesh.E;
             }
@@ -254,6 +261,7 @@ static int step_group(solve_server* S, int PP, std::vector<Solve*>& v, hipStream
             for (size_t i = 0; i < cn; ++i) {
                 Solve* s = v[c0 + i];
                 if (!s->req.use_nn) continue;
+                if (s->req.nn_after_step && stg != 0) continue;   // s(q^n) once, at the step start
                 NetTarget t;
                 t.q = s->q;
                 t.out = (double*)(s->ws + ws_layout(s->mesh).forcing);
@@ -291,7 +299,8 @@ static std::map<int, int64_t> round_plan(const std::map<int, std::vector<Solve*>
     double cmax = 0.0;
     for (auto& g : groups) {
         double c = 0.0;
-        for (Solve* s : g.second) c += (double)s->mesh.E * s->mesh.n_p * (s->req.use_nn ? 2.0 : 1.0);
+        for (Solve* s : g.second)
+            c += (double)s->mesh.E * s->mesh.n_p * (s->req.use_nn ? (s->req.nn_after_step ? 1.3 : 2.0) : 1.0);
         cost[g.first] = c;
         cmax = std::max(cmax, c);
     }
@@ -471,6 +480,7 @@ int solve_submit(solve_server* S, const solve_request* r, uint64_t* id) {
     if (!(r->Re > 0) || !(r->t_end > 0) || !std::isfinite(r->t_end) || r->ke_every < 1 || r->Cs < 0)
         return set_error(DG_EINVAL, "invalid request parameters");
     if (r->ke_host && r->ke_capacity < 0) return set_error(DG_EINVAL, "negative KE capacity");
+    if (r->nn_after_step != 0 && r->nn_after_step != 1) return set_error(DG_EINVAL, "nn_after_step must be 0 or 1");
     Mesh m;
     dg_params p = request_params(*r);
     int rc = make_mesh(&p, m);

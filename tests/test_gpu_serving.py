@@ -54,6 +54,7 @@ MIX = [
     dict(Re=1600.0, P=8, N=4, Cs=0.1),
     dict(Re=200.0, P=3, N=8, use_nn=True),
     dict(Re=30.0, P=6, N=2),
+    dict(Re=200.0, P=3, N=4, use_nn=True, after_step=True),
 ]
 
 
@@ -125,3 +126,26 @@ def test_invalid_requests(B):
     with pytest.raises(B.DGError):
         srv.submit(Re=-1.0, P=3, N=4, t_end=0.1)
     srv.close()
+
+
+@pytest.mark.parametrize("after_step", [False, True])
+def test_server_solve_equals_library_stepping(B, model, after_step):
+    """A corrected solve run by the server (forcing at every stage, or
+    Algorithm 1's correction after each step) ends in the same state as the
+    library's own stepper with the same time step, bitwise."""
+    say("serving vs library stepping", after_step)
+    N, P, Re, t_end = 4, 3, 200.0, 0.03
+    srv = B.Server(256 << 20, max_slots=4)
+    rid = srv.submit(Re=Re, P=P, N=N, t_end=t_end, use_nn=True, model=model, want_state=True, after_step=after_step)
+    st = _wait(srv, [rid])[rid]
+    assert st.state == B.SOLVE_DONE, st.error
+    _, q_srv = srv.results(rid)
+    srv.close()
+    m = B.Mesh(N, P, Re)
+    q = m.field()
+    B.dg_init_tgv(m, q)
+    k = m.field(0.0)
+    assert st.n_steps >= 1 and abs(st.dt * st.n_steps - t_end) < 1e-12
+    (B.dg_rk_step_post if after_step else B.dg_rk_step)(m, q, k, st.dt, st.n_steps, model=model)
+    torch.cuda.synchronize()
+    assert np.array_equal(q.cpu().numpy().ravel(), q_srv)
