@@ -41,16 +41,6 @@ __device__ __forceinline__ int find_solve(const DescList& dl, int b) {
     return s;
 }
 
-__device__ __forceinline__ int neighbour(int e, int N, int f) {
-    int ex = e % N, ey = (e / N) % N, ez = e / (N * N);
-    const int d = f >> 1;
-    const int step = (f & 1) ? 1 : N - 1;
-    if (d == 0) ex = (ex + step) % N;
-    else if (d == 1) ey = (ey + step) % N;
-    else ez = (ez + step) % N;
-    return ex + N * (ey + N * ez);
-}
-
 // The neighbour across face f of element e at coordinates (cx, cy, cz)
 // (uniform across the block), without an integer division per thread.
 __device__ __forceinline__ int neighbour_at(int e, int N, int cx, int cy, int cz, int f) {
