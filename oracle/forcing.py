@@ -36,17 +36,34 @@ MOMENTUM = (1, 2, 3)
 
 
 class Normalisation:
-    """Per-variable affine maps of the network input and output."""
+    """Affine maps of the network input and output: per variable (mu_in[5],
+    ...), or per node of the element row (columns: mu_in, sigma_in, mu_out,
+    sigma_out each of length 5 n_p, column v n_p + n), the paper's rescaling
+    of the values at each node (Sec. 2.2)."""
 
-    def __init__(self, mu_in, sigma_in, mu_out, sigma_out, mask=(1, 1, 1, 1, 1)):
+    def __init__(self, mu_in, sigma_in, mu_out, sigma_out, mask=(1, 1, 1, 1, 1), columns=None):
         self.mu_in = np.asarray(mu_in, dtype=np.float64)
         self.sigma_in = np.asarray(sigma_in, dtype=np.float64)
         self.mu_out = np.asarray(mu_out, dtype=np.float64)
         self.sigma_out = np.asarray(sigma_out, dtype=np.float64)
         self.mask = np.asarray(mask, dtype=np.float64)
+        self.columns = None if columns is None else [np.asarray(c, dtype=np.float64) for c in columns]
 
     def as_array(self):
         return np.concatenate([self.mu_in, self.sigma_in, self.mu_out, self.sigma_out])
+
+    def maps(self, iv, ov, n_p):
+        """(shift_in, scale_in, shift_out, scale_out) over the network's
+        input columns (variables iv) and output columns (variables ov)."""
+        if self.columns is None:
+            return (np.repeat(self.mu_in[iv], n_p), np.repeat(self.sigma_in[iv], n_p),
+                    np.repeat(self.mu_out[ov], n_p), np.repeat(self.sigma_out[ov], n_p))
+
+        def take(c, vs):
+            return np.concatenate([c[v * n_p:(v + 1) * n_p] for v in vs])
+
+        mi, si, mo, so = self.columns
+        return take(mi, iv), take(si, iv), take(mo, ov), take(so, ov)
 
 
 def element_rows(q_flat):
@@ -66,9 +83,10 @@ def network_forcing(q_flat, params, norm, act="tanh", in_vars=ALL_VARS, out_vars
     nv, E, n_p = q_flat.shape
     iv, ov = list(in_vars), list(out_vars)
     X = element_rows(q_flat[iv])
-    xhat = (X - np.repeat(norm.mu_in[iv], n_p)) / np.repeat(norm.sigma_in[iv], n_p)
+    shift_in, scale_in, shift_out, scale_out = norm.maps(iv, ov, n_p)
+    xhat = (X - shift_in) / scale_in
     yhat = mlp.forward(params, xhat, act)[-1]
-    s_sel = yhat * np.repeat(norm.sigma_out[ov], n_p) + np.repeat(norm.mu_out[ov], n_p)
+    s_sel = yhat * scale_out + shift_out
     s_sel = s_sel * np.repeat(norm.mask[ov], n_p)
     s = np.zeros_like(np.asarray(q_flat, dtype=np.float64))
     s[ov] = rows_to_field(s_sel, len(ov), n_p)
@@ -109,6 +127,22 @@ def normalisation_from_pairs(X, Y, nv=5):
     mi, si = stats(np.asarray(X, dtype=np.float64))
     mo, so = stats(np.asarray(Y, dtype=np.float64))
     return Normalisation(mi, si, mo, so)
+
+
+def column_normalisation_from_pairs(X, Y):
+    """Mean and standard deviation of every column (node of a variable) of
+    the training pairs, the standard deviation floored at 1e-12 max(1, |mean|);
+    the per-variable statistics are kept beside them."""
+    def stats(A):
+        A = np.asarray(A, dtype=np.float64)
+        mu = A.mean(axis=0)
+        sd = np.maximum(A.std(axis=0), 1e-12 * np.maximum(1.0, np.abs(mu)))
+        return mu, sd
+
+    base = normalisation_from_pairs(X, Y)
+    mi, si = stats(X)
+    mo, so = stats(Y)
+    return Normalisation(base.mu_in, base.sigma_in, base.mu_out, base.sigma_out, columns=(mi, si, mo, so))
 
 
 def increment_target(q_hi, prm_hi, prm_lo, dt_lo, m_sub):

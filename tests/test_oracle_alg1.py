@@ -143,3 +143,41 @@ def test_variable_selection():
     norm_full = forcing.Normalisation(norm.mu_in, norm.sigma_in, norm.mu_out, norm.sigma_out, mask=mask_full)
     s_full = forcing.network_forcing(q, full, norm_full, "relu")
     assert np.max(np.abs(s - s_full)) < 1e-13 * np.max(np.abs(s))
+
+
+def test_column_statistics_on_a_constructed_dataset():
+    """Column c of the constructed rows has mean c and standard deviation
+    c + 1 exactly (values c +- (c + 1) in alternate rows)."""
+    rows, cols = 10, 40
+    sign = np.where(np.arange(rows) % 2 == 0, 1.0, -1.0)[:, None]
+    c = np.arange(cols, dtype=np.float64)[None, :]
+    X = c + (c + 1) * sign
+    Y = -2.0 * X
+    n = forcing.column_normalisation_from_pairs(X, Y)
+    mi, si, mo, so = n.columns
+    assert np.allclose(mi, np.arange(cols), atol=1e-13) and np.allclose(si, np.arange(cols) + 1, atol=1e-13)
+    assert np.allclose(mo, -2 * np.arange(cols), atol=1e-12) and np.allclose(so, 2 * (np.arange(cols) + 1), atol=1e-12)
+
+
+def test_column_normalisation_maps_nodes_of_the_selected_variables():
+    """With equal input and output maps an identity network returns its
+    input, node by node, for the selected variables only; per-variable maps
+    are the special case of constant columns."""
+    rng = np.random.default_rng(14)
+    E, n_p = 3, 8
+    q = rng.standard_normal((5, E, n_p))
+    mu = rng.standard_normal(5 * n_p)
+    sd = rng.uniform(0.5, 2.0, 5 * n_p)
+    norm = forcing.Normalisation(np.zeros(5), np.ones(5), np.zeros(5), np.ones(5), columns=(mu, sd, mu, sd))
+    ident = [(np.eye(3 * n_p), np.zeros(3 * n_p))]
+    s = forcing.network_forcing(q, ident, norm, "tanh", forcing.MOMENTUM, forcing.MOMENTUM)
+    assert np.max(np.abs(s[1:4] - q[1:4])) < 1e-14 and np.all(s[[0, 4]] == 0)
+    # constant columns per variable = the per-variable normalisation
+    pv = rng.uniform(0.5, 2.0, 5)
+    pm = rng.standard_normal(5)
+    colw = forcing.Normalisation(pm, pv, pm[::-1], pv[::-1],
+                                 columns=(np.repeat(pm, n_p), np.repeat(pv, n_p), np.repeat(pm[::-1], n_p),
+                                          np.repeat(pv[::-1], n_p)))
+    varw = forcing.Normalisation(pm, pv, pm[::-1], pv[::-1])
+    params = [(rng.standard_normal((5 * n_p, 5 * n_p)) / 6, rng.standard_normal(5 * n_p))]
+    assert np.array_equal(forcing.network_forcing(q, params, colw), forcing.network_forcing(q, params, varw))
