@@ -201,6 +201,13 @@ int nn_init_io(const int32_t* dims, int32_t n_layers, int32_t activation,
 int nn_refresh(nn_model* model, void* stream);
 /* Replaces the normalisation (host array of 20 doubles) and the mask. */
 int nn_set_norm(nn_model* model, const double* norm, const uint8_t* mask);
+/* Per-node normalisation, the paper's rescaling of the values at each node
+ * (Sec. 2.2): col_dev (device, caller-owned, kept by reference until reset)
+ * holds [4][5 n_p] doubles -- mu_in, sigma_in, mu_out, sigma_out of each
+ * column v n_p + n of the five-variable element row -- and replaces the
+ * per-variable maps of nn_init (the mask still applies).  NULL returns to
+ * the per-variable maps.  DG_EINVAL when n_p does not fit the network. */
+int nn_set_column_norm(nn_model* model, const double* col_dev, int32_t n_p);
 void nn_free(nn_model* model);
 
 /* dqdt += s(q) for every element of mesh m (bfloat16 matrix-core products,
@@ -233,6 +240,13 @@ int nn_train_step(nn_model* model, const float* x, const float* y, const int32_t
  * floored at 1e-12 max(1, |mu|).  Two-pass float64 reduction on the device,
  * fixed order.  Synchronises `stream`; ws must hold nn_stats_ws(rows) bytes. */
 size_t nn_stats_ws(int64_t rows);
+/* Per-column mean and standard deviation of a training set (rows of 5 n_p
+ * floats): out_dev (device) receives [4][5 n_p] doubles in nn_set_column_norm's
+ * layout; each sigma floored at 1e-12 max(1, |mu|).  Two-pass float64
+ * reduction, fixed order; ws must hold nn_column_stats_ws(rows, n_p) bytes. */
+size_t nn_column_stats_ws(int64_t rows, int32_t n_p);
+int nn_column_stats(const float* x, const float* y, int64_t rows, int32_t n_p, double* out_dev,
+                    void* ws, size_t ws_bytes, void* stream);
 int nn_data_stats(const float* x, const float* y, int64_t rows, int32_t n_p, double* out_host,
                   void* ws, size_t ws_bytes, void* stream);
 

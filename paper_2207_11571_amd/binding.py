@@ -76,6 +76,9 @@ SIGNATURES = {
                                   ctypes.POINTER(ctypes.c_uint8), _vp, _vp, _vp, _vp, _vp,
                                   ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_uint8), _vp, ctypes.POINTER(_vp)]),
     "nn_refresh": (ctypes.c_int, [_vp, _vp]),
+    "nn_set_column_norm": (ctypes.c_int, [_vp, _vp, _i32]),
+    "nn_column_stats_ws": (_sz, [_i64, _i32]),
+    "nn_column_stats": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp, _sz, _vp]),
     "nn_set_norm": (ctypes.c_int, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_uint8)]),
     "nn_free": (None, [_vp]),
     "nn_forcing": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -313,6 +316,17 @@ class Model:
         msk = (ctypes.c_uint8 * 5)(*[1 if x else 0 for x in mask]) if mask is not None else None
         check(lib().nn_set_norm(self.handle, nrm, msk))
 
+    def set_column_norm(self, col, n_p):
+        """Per-node normalisation: col is a device float64 tensor [4, 5 n_p]
+        (mu_in, sigma_in, mu_out, sigma_out per row column), kept alive here;
+        None returns to the per-variable maps."""
+        if col is None:
+            self.col_norm = None
+            check(lib().nn_set_column_norm(self.handle, None, 0))
+            return
+        self.col_norm = col.contiguous()
+        check(lib().nn_set_column_norm(self.handle, _ptr(self.col_norm, torch.float64, "col"), n_p))
+
     def refresh(self, stream=None):
         check(lib().nn_refresh(self.handle, _stream(stream)))
 
@@ -348,6 +362,16 @@ def nn_data_stats(x, y, n_p, stream=None):
     check(lib().nn_data_stats(_ptr(x, torch.float32, "x"), _ptr(y, torch.float32, "y"), rows, n_p, out, _ptr(ws),
                               ws.numel(), _stream(stream)))
     return list(out)
+
+
+def nn_column_stats(x, y, n_p, stream=None):
+    """Device float64 tensor [4, 5 n_p]: per-column mu_x, sigma_x, mu_y, sigma_y."""
+    rows = x.shape[0]
+    ws = torch.empty(max(1, lib().nn_column_stats_ws(rows, n_p)), dtype=torch.uint8, device=x.device)
+    out = torch.empty((4, 5 * n_p), dtype=torch.float64, device=x.device)
+    check(lib().nn_column_stats(_ptr(x, torch.float32, "x"), _ptr(y, torch.float32, "y"), rows, n_p,
+                                _ptr(out, torch.float64, "out"), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
 
 
 def solve_footprint(P, N, use_nn=False):

@@ -82,6 +82,10 @@ struct NetArgs {
     // node n of variable in_var[j]) and forces out_var[0..n_out) likewise
     int n_in, n_out;
     int in_var[5], out_var[5];
+    // per-node normalisation (null: per variable): device [4][5 col_np] doubles,
+    // mu_in, sigma_in, mu_out, sigma_out of row column v col_np + n
+    const double* col;
+    int col_np;
 };
 
 // One network application target for the batched forcing kernel: the
@@ -185,6 +189,8 @@ hipError_t launch_grads(const GradArgs& ga, hipStream_t st);
 hipError_t launch_loss_final(const float* part, int n, float inv_count, float* loss, hipStream_t st);
 hipError_t launch_data_stats(const float* x, const float* y, int64_t rows, int n_p, double* part, int nblocks,
                              double* out_dev, hipStream_t st);
+hipError_t launch_column_stats(const float* x, const float* y, int64_t rows, int ncols, double* part, int nblocks,
+                               double* out_dev, hipStream_t st);
 hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t n, const ParamMap& pm,
                        uint16_t* wbf, float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st);
 

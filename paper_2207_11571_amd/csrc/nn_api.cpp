@@ -68,6 +68,8 @@ NetArgs net_args(const nn_model* m) {
     }
     na.n_in = m->n_in;
     na.n_out = m->n_out;
+    na.col = m->col_norm;
+    na.col_np = m->col_np;
     return na;
 }
 
@@ -77,6 +79,9 @@ int net_check_mesh(const nn_model* m, const Mesh& mesh) {
         return set_error(DG_EINVAL, "network sizes %d -> %d do not match %d and %d variables x %d nodes per element",
                          m->dims[0], m->dims[m->n_layers], m->n_in, m->n_out, mesh.n_p);
     if (m->device != mesh.device) return set_error(DG_EINVAL, "model and mesh live on different devices");
+    if (m->col_norm && m->col_np != mesh.n_p)
+        return set_error(DG_EINVAL, "per-node normalisation is for %d nodes per element, the mesh has %d", m->col_np,
+                         mesh.n_p);
     return DG_OK;
 }
 
@@ -249,6 +254,21 @@ int nn_set_norm(nn_model* m, const double* norm, const uint8_t* mask) {
     return DG_OK;
 }
 
+int nn_set_column_norm(nn_model* m, const double* col_dev, int32_t n_p) {
+    if (!m) return set_error(DG_EINVAL, "null model");
+    if (!col_dev) {
+        m->col_norm = nullptr;
+        m->col_np = 0;
+        return DG_OK;
+    }
+    if (n_p < 1 || m->dims[0] != m->n_in * n_p || m->dims[m->n_layers] != m->n_out * n_p)
+        return set_error(DG_EINVAL, "n_p = %d does not fit the network sizes", n_p);
+    if (((uintptr_t)col_dev) & 7) return set_error(DG_EINVAL, "normalisation array must be 8-byte aligned");
+    m->col_norm = col_dev;
+    m->col_np = n_p;
+    return DG_OK;
+}
+
 void nn_free(nn_model* m) { delete m; }
 
 int nn_forcing(const nn_model* m, const dg_mesh* mesh_h, const double* q, double* dqdt, void* ws, size_t ws_bytes,
@@ -342,6 +362,22 @@ int nn_train_step(nn_model* m, const float* x, const float* y, const int32_t* id
     }
     NN_HIP(launch_adam(m->params, m->grad, m->adam_m, m->adam_v, m->n_params, pm, m->wbf, lr, 0.9f, 0.999f, 1e-7f,
                        (float)bc1, (float)bc2, st));
+    return DG_OK;
+}
+
+size_t nn_column_stats_ws(int64_t rows, int32_t n_p) {
+    if (rows < 1 || n_p < 1) return 0;
+    const int nb = (int)(rows < 512 ? rows : 512);
+    return align256((size_t)nb * 2 * 5 * n_p * sizeof(double));
+}
+
+int nn_column_stats(const float* x, const float* y, int64_t rows, int32_t n_p, double* out_dev, void* ws,
+                    size_t ws_bytes, void* stream) {
+    if (!x || !y || !out_dev || rows < 1 || n_p < 1) return set_error(DG_EINVAL, "bad arguments");
+    if (!ws || (((uintptr_t)ws) & 255)) return set_error(DG_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < nn_column_stats_ws(rows, n_p)) return set_error(DG_ENOSPC, "workspace too small");
+    const int nb = (int)(rows < 512 ? rows : 512);
+    NN_HIP(launch_column_stats(x, y, rows, 5 * n_p, (double*)ws, nb, out_dev, (hipStream_t)stream));
     return DG_OK;
 }
 

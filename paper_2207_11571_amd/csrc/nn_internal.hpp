@@ -24,6 +24,8 @@ struct nn_model {
     int n_in = 5, n_out = 5;                 // variables read / forced
     int in_var[5] = {0, 1, 2, 3, 4};
     int out_var[5] = {0, 1, 2, 3, 4};
+    const double* col_norm = nullptr;        // per-node normalisation (device, caller-owned) or null
+    int col_np = 0;
     int64_t step = 0;                        // Adam step counter
     int device = 0;
 };

@@ -135,7 +135,13 @@ __global__ void __launch_bounds__(kRowThreads) k_net_forcing(NetArgs na, int NP,
         if (e < E && c < din) {
             const int j = c / NP, n = c - j * NP;
             const int v = na.in_var[j];
-            x = (float)((T.q[v * vs + (size_t)e * NP + n] - na.mu_in[v]) / na.sig_in[v]);
+            const double qv = T.q[v * vs + (size_t)e * NP + n];
+            if (na.col) {
+                const int cc = v * NP + n;
+                x = (float)((qv - na.col[cc]) / na.col[5 * NP + cc]);
+            } else {
+                x = (float)((qv - na.mu_in[v]) / na.sig_in[v]);
+            }
         }
         bufA[r * ld + c] = f2bf(x);
     }
@@ -169,7 +175,9 @@ __global__ void __launch_bounds__(kRowThreads) k_net_forcing(NetArgs na, int NP,
                     const float y = v + bias[n];
                     const int j = n / NP, node = n - j * NP;
                     const int vv = na.out_var[j];
-                    const double s = na.mask[vv] * (na.sig_out[vv] * (double)y + na.mu_out[vv]);
+                    const int cc = vv * NP + node;
+                    const double s = na.col ? na.mask[vv] * (na.col[15 * NP + cc] * (double)y + na.col[10 * NP + cc])
+                                            : na.mask[vv] * (na.sig_out[vv] * (double)y + na.mu_out[vv]);
                     double* o = T.out + vv * vs + (size_t)e * NP + node;
                     *o = accumulate ? *o + s : s;
                 }
@@ -237,7 +245,13 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
             const int j = c / npv_in, n = c - j * npv_in;
             const int v = na.in_var[j];
             const size_t src = ta.idx ? (size_t)ta.idx[row] : (size_t)row;
-            x = (float)((ta.x[src * xw + (size_t)v * npv_in + n] - na.mu_in[v]) / na.sig_in[v]);
+            const double xv = ta.x[src * xw + (size_t)v * npv_in + n];
+            if (na.col) {
+                const int cc = v * npv_in + n;
+                x = (float)((xv - na.col[cc]) / na.col[5 * npv_in + cc]);
+            } else {
+                x = (float)((xv - na.mu_in[v]) / na.sig_in[v]);
+            }
         }
         act[0][r * ld + c] = f2bf(x);
     }
@@ -269,8 +283,10 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
                 const int j = n / npv_out, nn = n - j * npv_out;
                 const int vv = na.out_var[j];
                 const size_t src = ta.idx ? (size_t)ta.idx[row] : (size_t)row;
-                const float yt =
-                    (float)((ta.y[src * yw + (size_t)vv * npv_out + nn] - na.mu_out[vv]) / na.sig_out[vv]);
+                const double yv = ta.y[src * yw + (size_t)vv * npv_out + nn];
+                const int cc = vv * npv_out + nn;
+                const float yt = na.col ? (float)((yv - na.col[10 * npv_out + cc]) / na.col[15 * npv_out + cc])
+                                        : (float)((yv - na.mu_out[vv]) / na.sig_out[vv]);
                 const float diff = v + bias[n] - yt;
                 lsum += diff * diff;
                 dy = ta.grad_scale * diff;
@@ -515,6 +531,44 @@ __global__ void k_stats_final(const double* __restrict__ part, int nblocks, doub
     }
 }
 
+// Per-column statistics of a training set (x and y rows of ncols floats):
+// block b sums its contiguous chunk of rows for every column (pass 0 values,
+// pass 1 squared deviations from the pass-0 means), the final kernel sums the
+// block partials in order.  out: [4][ncols] = mu_x, sigma_x, mu_y, sigma_y.
+__global__ void __launch_bounds__(256) k_colstats_partial(const float* __restrict__ x, const float* __restrict__ y,
+                                                         int64_t rows, int ncols, const double* __restrict__ out,
+                                                         int pass, double* __restrict__ part) {
+    const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < rows ? r0 + per : rows;
+    for (int c = threadIdx.x; c < 2 * ncols; c += 256) {
+        const float* A = c < ncols ? x : y;
+        const int cc = c < ncols ? c : c - ncols;
+        const double mu = pass ? out[(c < ncols ? 0 : 2 * ncols) + cc] : 0.0;
+        double s = 0.0;
+        for (int64_t r = r0; r < r1; ++r) {
+            const double v = (double)A[r * ncols + cc] - mu;
+            s += pass ? v * v : v;
+        }
+        part[(size_t)blockIdx.x * 2 * ncols + c] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_colstats_final(const double* __restrict__ part, int nblocks, int ncols,
+                                                       double count, int pass, double* __restrict__ out) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= 2 * ncols) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * 2 * ncols + c];
+    const int base = c < ncols ? 0 : 2 * ncols, cc = c < ncols ? c : c - ncols;
+    if (pass == 0) {
+        out[base + cc] = s / count;
+    } else {
+        const double mu = out[base + cc];
+        out[base + ncols + cc] = fmax(sqrt(s / count), 1e-12 * fmax(1.0, fabs(mu)));
+    }
+}
+
 // ------------------------------------------------------------ host launchers
 
 hipError_t launch_data_stats(const float* x, const float* y, int64_t rows, int n_p, double* part, int nblocks,
@@ -619,6 +673,18 @@ hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, st, params, grad, m, v, n, pm, wbf, lr, b1, b2, eps, bc1,
                        bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_column_stats(const float* x, const float* y, int64_t rows, int ncols, double* part, int nblocks,
+                               double* out, hipStream_t st) {
+    const int fb = (2 * ncols + 255) / 256;
+    const double count = (double)rows;
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_colstats_partial, dim3(nblocks), dim3(256), 0, st, x, y, rows, ncols,
+                           (const double*)out, pass, part);
+        hipLaunchKernelGGL(k_colstats_final, dim3(fb), dim3(256), 0, st, part, nblocks, ncols, count, pass, out);
+    }
     return hipGetLastError();
 }
 

@@ -48,12 +48,16 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def variant(name, target="eq5", io="all", act="tanh", mode="stage", epochs=30, lr=1e-3, mask=(1, 1, 1, 1, 1)):
+def variant(name, target="eq5", io="all", act="tanh", mode="stage", epochs=30, lr=1e-3, mask=(1, 1, 1, 1, 1),
+            scaling="variable"):
     """One network to train and evaluate.  target: "eq5" or "alg1" pairs; io:
     "all" (reads and forces the five variables) or "momentum" (the paper's
     network, Sec. 2.2); mode: "stage" (forcing at every stage) or "post"
-    (Algorithm 1's correction after each step)."""
-    return dict(name=name, target=target, io=io, act=act, mode=mode, epochs=epochs, lr=lr, mask=tuple(mask))
+    (Algorithm 1's correction after each step); scaling: "variable" (one
+    affine map per variable) or "node" (per node of the element, the paper's
+    rescaling of the values at each node)."""
+    return dict(name=name, target=target, io=io, act=act, mode=mode, epochs=epochs, lr=lr, mask=tuple(mask),
+                scaling=scaling)
 
 
 class Reference:
@@ -160,6 +164,8 @@ def train(X, Y, n_p, v, batch, seed=0, norm=None, init_params=None, log=print):
         norm = B.nn_data_stats(X, Y, n_p)
     params = init_params.clone() if init_params is not None else B.pack_params(synthetic.mlp_init(dims, seed=seed))
     model = B.Model(dims, params, norm, mask=v["mask"], activation=v["act"], in_vars=io, out_vars=io)
+    if v.get("scaling", "variable") == "node":
+        model.set_column_norm(B.nn_column_stats(X, Y, n_p), n_p)
     rng = np.random.default_rng(seed)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     losses = []
@@ -431,8 +437,10 @@ def run_online(N=8, Re=200.0, P_lo=3, t0=4.0, t_end=7.0, window=0.15, snapshots=
 def _variants(spec):
     out = []
     for item in spec.split(";"):
-        name, target, io, act, mode, ep, lr = item.split(":")
-        out.append(variant(name, target, io, act, mode, int(ep), float(lr)))
+        f = item.split(":")
+        name, target, io, act, mode, ep, lr = f[:7]
+        out.append(variant(name, target, io, act, mode, int(ep), float(lr),
+                           scaling=f[7] if len(f) > 7 else "variable"))
     return out
 
 

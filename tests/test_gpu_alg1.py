@@ -231,3 +231,69 @@ def test_stage_forcing_with_momentum_network(B):
     e_corr = rel_l2(got - dg.to_flat(q_unc), corr_ref)
     print("accumulated correction rel L2", e_corr)
     assert e_corr < 2e-2
+
+
+def _rows(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.empty((n, 320), dtype=np.float32)
+    x[:, :64] = 1.0 + 0.01 * rng.standard_normal((n, 64))
+    x[:, 64:256] = rng.standard_normal((n, 192)) * np.linspace(0.5, 2.0, 192)[None, :]
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((n, 64))
+    y = (1e-2 * rng.standard_normal((n, 320)) * np.linspace(0.2, 3.0, 320)[None, :]).astype(np.float32)
+    return x, y
+
+
+def test_column_stats_match_oracle(B):
+    from oracle import forcing
+    say("column stats")
+    x, y = _rows(3000, 21)
+    y[:, 5] = 0.25                     # a constant column: its sigma hits the floor
+    got = B.nn_column_stats(_to_gpu(x, np.float32), _to_gpu(y, np.float32), 64).cpu().numpy()
+    ref = np.stack(forcing.column_normalisation_from_pairs(x, y).columns)
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)) < 1e-10
+
+
+def test_per_node_normalisation_forcing_and_gradients(B):
+    """The momentum relu network with per-node maps (the paper's rescaling at
+    each node): forcing and one training step's gradients vs the oracle."""
+    from oracle import dg, forcing, mlp
+    say("per-node normalisation")
+    x, y = _rows(512, 22)
+    col = B.nn_column_stats(_to_gpu(x, np.float32), _to_gpu(y, np.float32), 64)
+    cn = [c for c in col.cpu().numpy()]
+    layers = synthetic.mlp_init(DIMS, seed=5)
+    layers = [(W, b + 0.01) for W, b in layers]
+    params, norm = _oracle_model(layers)
+    norm = forcing.Normalisation(norm.mu_in, norm.sigma_in, norm.mu_out, norm.sigma_out, columns=cn)
+    model = B.Model(DIMS, B.pack_params(layers), NORM, activation="relu", in_vars=MOM, out_vars=MOM)
+    model.set_column_norm(col, 64)
+    prm, q = _state(3, 3, 400.0, seed=9)
+    qf = dg.to_flat(q)
+    m = B.Mesh(3, 3, 400.0)
+    out = m.field(0.0)
+    B.nn_forcing(model, m, _to_gpu(qf), out)
+    got = out.cpu().numpy()
+    ref = forcing.network_forcing(qf, params, norm, "relu", MOM, MOM)
+    err = rel_l2(got, ref)
+    print("forcing rel L2", err)
+    assert err < 1e-2 and not got[[0, 4]].any()
+    # back to the per-variable maps and again per node
+    model.set_column_norm(None, 0)
+    out2 = m.field(0.0)
+    B.nn_forcing(model, m, _to_gpu(qf), out2)
+    ref2 = forcing.network_forcing(qf, params, _oracle_model(layers)[1], "relu", MOM, MOM)
+    assert rel_l2(out2.cpu().numpy(), ref2) < 1e-2
+    model.set_column_norm(col, 64)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    B.nn_train_step(model, _to_gpu(x, np.float32), _to_gpu(y, np.float32), lr=1e-3, loss=loss)
+    torch.cuda.synchronize()
+    shift_in, scale_in, shift_out, scale_out = norm.maps(list(MOM), list(MOM), 64)
+    xh = (x[:, 64:256].astype(np.float64) - shift_in) / scale_in
+    yt = (y[:, 64:256].astype(np.float64) - shift_out) / scale_out
+    loss_ref, grads = mlp.mse_loss_and_grads(params, xh, yt, "relu", quantise=True)
+    assert abs(loss.item() / loss_ref - 1) < 1e-2
+    g_gpu = B.unpack_params(model.grad.cpu().numpy().astype(np.float64), DIMS)
+    for l, ((gW, gb), (rW, rb)) in enumerate(zip(g_gpu, grads)):
+        eW, eb = rel_l2(gW, rW), rel_l2(gb, rb)
+        print("layer", l, "grad rel L2", eW, eb)
+        assert eW < 1e-2 and eb < 1e-2
