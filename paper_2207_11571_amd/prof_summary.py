@@ -2,6 +2,7 @@
 
     python -m paper_2207_11571_amd.prof_summary trace <dir> "<command>" > profiles/<name>.md
     python -m paper_2207_11571_amd.prof_summary counters <dir> <kernel-substring> <copy-bytes> "<command>"
+    python -m paper_2207_11571_amd.prof_summary sq <dir1,dir2,...> "<kernel1;kernel2;...>" "<command>"
 
 `trace` reads the kernel dispatches of a --kernel-trace run (rocpd SQLite
 database or kernel_stats/kernel_trace CSV) and prints per-kernel count, mean,
@@ -90,10 +91,37 @@ def counters(d, kernel, copy_bytes, command):
     print(f"- bytes per dispatch (scaled): {mean_k * 1024.0 * factor:.0f}")
 
 
+def sq(dirs, kernels, command):
+    """Mean per-dispatch SQ counters of the named kernels over several --pmc
+    runs (one counter set each), also per wavefront (divided by SQ_WAVES)."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for d in dirs:
+        for name, _, pmc in _dispatches(d):
+            for k in kernels:
+                if k in name:
+                    for c, v in pmc.items():
+                        vals[k][c].append(v)
+    print(f"Command (one run per counter set): `{command}`\n")
+    for k in kernels:
+        m = {c: sum(v) / len(v) for c, v in vals[k].items()}
+        if not m:
+            continue
+        waves = m.get("SQ_WAVES", 0.0)
+        print(f"### `{k}`\n")
+        print("| counter | per dispatch | per wavefront |")
+        print("|---|---|---|")
+        for c in sorted(m):
+            pw = f"{m[c] / waves:.1f}" if waves else ""
+            print(f"| {c} | {m[c]:.0f} | {pw} |")
+        print()
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[3])
     elif sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5])
+    elif sys.argv[1] == "sq":
+        sq(sys.argv[2].split(","), sys.argv[3].split(";"), sys.argv[4])
     else:
         raise SystemExit(__doc__)
