@@ -30,6 +30,13 @@ struct Shape {
     static constexpr int NT = ((NP + 63) / 64) * 64;
     static constexpr int NFT = 6 * NF;                  // face-node tasks
     static constexpr int TPT = (NFT + NT - 1) / NT;     // tasks per thread
+    // minimum wavefronts per SIMD that the stage kernels are compiled for:
+    // five lets three blocks of 4 - 6 wavefronts share a CU (P = 4 - 6;
+    // P = 3 is bound by LDS, P >= 7 by the registers it needs), where the
+    // kernel fits the registers that leaves without spilling (k_grad at
+    // P = 6 does not, and is slower at five)
+    static constexpr int WPE = (PP >= 5 && PP <= 7) ? 5 : 2;
+    static constexpr int GRAD_WPE = (PP == 5 || PP == 6) ? 5 : 2;
 };
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
@@ -199,11 +206,18 @@ __device__ __forceinline__ void flux_viscous(double rho, const double v[3], cons
 }
 
 // Node quantities that the three directions of the volume flux share:
-// velocity, p - p_ref (momentum rows), rho E + p (energy row), and the
-// effective mu, kappa and (2/3) mu div v.
+// velocity, p - p_ref (momentum rows), rho E + p (energy row) and, viscous,
+// the symmetric stress tau (tau_00, tau_11, tau_22, tau_01, tau_02, tau_12,
+// with the Smagorinsky viscosity when on) and the energy rows
+// sum_a v_a tau_aD + kappa dT/dx_D of the three directions.  The gradient is
+// dead after this, which keeps the register budget of the volume phase low.
 struct NodeState {
-    double v[3], pt, pe, mu, kappa, lam;
+    double v[3], pt, pe, tau[6], ev[3];
 };
+
+__device__ __forceinline__ int sym_index(int a, int b) {
+    return a == b ? a : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5));
+}
 
 __device__ __forceinline__ void node_state(const double q[5], const double g[3][4], const Phys& ph, NodeState& n) {
     const double ir = recip(q[0]);
@@ -214,16 +228,31 @@ __device__ __forceinline__ void node_state(const double q[5], const double g[3][
     n.pt = p - ph.p_ref;
     n.pe = q[4] + p;
     if (ph.viscous) {
-        effective_visc(q[0], g, ph, n.mu, n.kappa);
-        n.lam = (2.0 / 3.0) * n.mu * (g[0][0] + g[1][1] + g[2][2]);
+        double mu, kappa;
+        effective_visc(q[0], g, ph, mu, kappa);
+        const double lam = (2.0 / 3.0) * mu * (g[0][0] + g[1][1] + g[2][2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) {
+                double t = mu * (g[a][b] + g[b][a]);
+                if (a == b) t -= lam;
+                n.tau[sym_index(a, b)] = t;
+            }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double e = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) e += n.v[a] * n.tau[sym_index(a, d)];
+            n.ev[d] = e + kappa * g[d][3];
+        }
     }
 }
 
 // net volume flux along D: inviscid (App. A, p_ref removed from the momentum
 // rows) minus viscous
 template <int D>
-__device__ __forceinline__ void flux_net(const double q[5], const double g[3][4], const NodeState& n,
-                                         const Phys& ph, double G[5]) {
+__device__ __forceinline__ void flux_net(const double q[5], const NodeState& n, const Phys& ph, double G[5]) {
     const double vd = n.v[D];
     G[0] = q[1 + D];
     G[1] = q[1] * vd;
@@ -232,15 +261,9 @@ __device__ __forceinline__ void flux_net(const double q[5], const double g[3][4]
     G[1 + D] += n.pt;
     G[4] = n.pe * vd;
     if (ph.viscous) {
-        double e = 0.0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double tau = n.mu * (g[a][D] + g[D][a]);
-            if (a == D) tau -= n.lam;
-            G[1 + a] -= tau;
-            e += n.v[a] * tau;
-        }
-        G[4] -= e + n.kappa * g[D][3];
+        for (int a = 0; a < 3; ++a) G[1 + a] -= n.tau[sym_index(a, D)];
+        G[4] -= n.ev[D];
     }
 }
 
@@ -432,7 +455,8 @@ __global__ void __launch_bounds__(Shape<PP>::NT) k_traces(DescList dl) {
 
 // BR1 pass: one-sided viscous normal fluxes on the six faces of each element.
 template <int PP>
-__global__ void __launch_bounds__(Shape<PP>::NT) k_grad(DescList dl) {
+__global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::GRAD_WPE)))
+k_grad(DescList dl) {
     using S = Shape<PP>;
     constexpr int NP = S::NP, NF = S::NF;
     constexpr int LDS = cmax(12 * NP, 5 * NP + 24 * NF);
@@ -528,7 +552,7 @@ __global__ void __launch_bounds__(Shape<PP>::NT) k_grad(DescList dl) {
 // Residual (update == 0: out = p(q) + forcing) or Runge-Kutta stage
 // (update == 1: k <- A k + dt R, q <- q + B k, traces of the new q).
 template <int PP, int UPDATE>
-__global__ void __launch_bounds__(Shape<PP>::NT)
+__global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::WPE)))
 k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     using S = Shape<PP>;
     constexpr int NP = S::NP, NF = S::NF;
@@ -547,13 +571,9 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     const size_t node = (size_t)e * NP + t;
     const size_t vstride = (size_t)E * NP;
 
-    double qn[5];
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            qn[v] = D.q[v * vstride + node];
-            sh[v * NP + t] = qn[v];
-        }
+        for (int v = 0; v < 5; ++v) sh[v * NP + t] = D.q[v * vstride + node];
     }
     __syncthreads();
 
@@ -596,6 +616,13 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     }
     __syncthreads();
 
+    // the node's own state, read back after the face phase so that it holds
+    // no registers there
+    double qn[5];
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qn[v] = sh[v * NP + t];
+    }
     double g[3][4];
     if (ph.viscous) {
         if (t < NP) {
@@ -625,9 +652,9 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
         __syncthreads();
         if (t < NP) {
             double G[5];
-            if (d == 0) flux_net<0>(qn, g, ns, ph, G);
-            else if (d == 1) flux_net<1>(qn, g, ns, ph, G);
-            else flux_net<2>(qn, g, ns, ph, G);
+            if (d == 0) flux_net<0>(qn, ns, ph, G);
+            else if (d == 1) flux_net<1>(qn, ns, ph, G);
+            else flux_net<2>(qn, ns, ph, G);
 #pragma unroll
             for (int v = 0; v < 5; ++v) sh[v * NP + t] = G[v];
         }
