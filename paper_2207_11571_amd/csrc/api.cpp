@@ -92,6 +92,21 @@ static void host_basis(int P, BasisTab& T) {
         for (int k = 0; k < n; ++k) den += lam[k] / (t - x[k]);
         for (int j = 0; j < n; ++j) (side ? bp : bm)[j] = (lam[j] / (t - x[j])) / den;
     }
+    for (int side = 0; side < 2; ++side) {
+        const long double* b = side ? bp : bm;
+        long double lp = 0.0L, lm = 0.0L;
+        for (int m = 0; m < n; ++m) {
+            lp += b[m] * bp[m] / w[m];
+            lm += b[m] * bm[m] / w[m];
+        }
+        T.lface_p[side] = (double)lp;
+        T.lface_m[side] = (double)lm;
+        for (int l = 0; l < n; ++l) {
+            long double acc = 0.0L;
+            for (int m = 0; m < n; ++m) acc += b[m] * (D[l][m] * w[l] / w[m]);
+            T.dface[side][l] = (double)acc;
+        }
+    }
     for (int i = 0; i < n; ++i) {
         T.nodes[i] = (double)x[i];
         T.w[i] = (double)w[i];

@@ -453,10 +453,10 @@ __global__ void __launch_bounds__(Shape<PP>::NT) k_traces(DescList dl) {
     write_traces<PP>(sh, B, t, e, D.qtr_out);
 }
 
-// BR1 pass: one-sided viscous normal fluxes on the six faces of each element.
+// BR1 pass, volume form: the lifted gradient at every node, then its face
+// interpolation.
 template <int PP>
-__global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::GRAD_WPE)))
-k_grad(DescList dl) {
+__device__ __forceinline__ void grad_volume_form(const DescList& dl) {
     using S = Shape<PP>;
     constexpr int NP = S::NP, NF = S::NF;
     constexpr int LDS = cmax(12 * NP, 5 * NP + 24 * NF);
@@ -547,6 +547,174 @@ k_grad(DescList dl) {
             for (int c = 0; c < 4; ++c) o[c * NF] = Fv[c];
         }
     }
+}
+
+// BR1 pass, face form: only the face values of the lifted gradient are needed here, so they are
+// formed on the faces directly (sum factorisation): the normal derivative as
+// one line contraction with the end-evaluated derivative row, the two
+// tangential derivatives as contractions of the face trace of w along the
+// face, with the lifting terms of the tangential faces interpolated to the
+// face's edges.  The result equals the face interpolation of the volume
+// gradient up to rounding, at O(P^3) instead of O(P^4) work per element.
+template <int PP>
+__device__ __forceinline__ void grad_face_form(const DescList& dl) {
+    using S = Shape<PP>;
+    constexpr int NP = S::NP, NF = S::NF;
+    constexpr int NET = 24 * PP;                 // edge tasks: 6 faces x 2 tangential axes x 2 sides x PP
+    __shared__ double sh[5 * NP + 48 * NF + 4 * NET];
+    double* what = sh + 5 * NP;                  // [6][4][NF] common BR1 values
+    double* wf = what + 24 * NF;                 // [6][4][NF] face traces of w
+    double* edge = wf + 24 * NF;                 // [6][2][2][4][PP] lifting values at the face edges
+    const int b = blockIdx.x;
+    const int si = find_solve(dl, b);
+    const SolveDesc& D = *dl.d[si];
+    const Phys ph = D.ph;
+    const int e = b - dl.blk[si];
+    const int ecx = e % D.N, ecy = (e / D.N) % D.N, ecz = e / (D.N * D.N);
+    const int E = D.E;
+    const int t = threadIdx.x;
+    const BasisTab& B = c_basis[PP - 2];
+
+    double qn[5];
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qn[v] = D.q[((size_t)v * E + e) * NP + t];
+            sh[v * NP + t] = qn[v];
+        }
+    }
+    __syncthreads();
+
+    double fq[S::TPT][4];   // own traced (rho, u, v, w) per face task
+#pragma unroll
+    for (int r = 0; r < S::TPT; ++r) {
+        const int tau = t + r * S::NT;
+        if (tau < S::NFT) {
+            const int f = tau / NF, fn = tau - f * NF;
+            double qi[5], qo[5];
+            face_interp<PP, 5>(sh, B, f, fn, qi);
+            const int nb = neighbour_at(e, D.N, ecx, ecy, ecz, f);
+            const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qo[v] = tr[v * NF];
+            double wi[4], wo[4];
+            gradient_vars(qi, ph.gm1, wi);
+            gradient_vars(qo, ph.gm1, wo);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) what[(f * 4 + c) * NF + fn] = 0.5 * (wi[c] + wo[c]);
+            fq[r][0] = qi[0];
+            fq[r][1] = wi[0];
+            fq[r][2] = wi[1];
+            fq[r][3] = wi[2];
+        }
+    }
+    __syncthreads();
+    if (t < NP) {
+        double w[4];
+        gradient_vars(qn, ph.gm1, w);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sh[c * NP + t] = w[c];
+    }
+    // edge values: the common values of a tangential face pair (axis dp,
+    // side sg), interpolated along the face normal to the face's edge
+    for (int tau = t; tau < NET; tau += S::NT) {
+        const int r = tau % PP, rest = tau / PP;
+        const int sg = rest & 1, u = (rest >> 1) & 1, f = rest >> 2;
+        const int d = f >> 1;
+        const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+        const int dp = u ? t1 : t0, dpp = u ? t0 : t1;
+        const double* bv = (f & 1) ? B.bp : B.bm;
+        const double* src = what + (2 * dp + sg) * 4 * NF;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < PP; ++m) {
+            const int fnp = d < dpp ? m + PP * r : r + PP * m;
+            const double c0 = bv[m];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] += c0 * src[c * NF + fnp];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) edge[(rest * 4 + c) * PP + r] = acc[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < S::TPT; ++r) {
+        const int tau = t + r * S::NT;
+        if (tau < S::NFT) {
+            const int f = tau / NF, fn = tau - f * NF;
+            double wv[4];
+            face_interp<PP, 4>(sh, B, f, fn, wv);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) wf[(f * 4 + c) * NF + fn] = wv[c];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < S::TPT; ++r) {
+        const int tau = t + r * S::NT;
+        if (tau < S::NFT) {
+            const int f = tau / NF, fn = tau - f * NF;
+            const int d = f >> 1, sd = f & 1;
+            const int a = fn % PP, bb = fn / PP;
+            // normal derivative: the line's weak derivative at this end
+            double gn[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < PP; ++l) {
+                const double c0 = B.dface[sd][l];
+                const int n = line_node<PP>(d, a, bb, l);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) gn[c] += c0 * sh[c * NP + n];
+            }
+            const double lp = B.lface_p[sd], lm = B.lface_m[sd];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                gn[c] = ph.s * (lp * what[((2 * d + 1) * 4 + c) * NF + fn] - lm * what[(2 * d * 4 + c) * NF + fn] - gn[c]);
+            // tangential derivatives along the face's first (a) and second (b) axis
+            double ga[4] = {0.0, 0.0, 0.0, 0.0}, gb[4] = {0.0, 0.0, 0.0, 0.0};
+            const double* wfp = wf + f * 4 * NF;
+#pragma unroll
+            for (int l = 0; l < PP; ++l) {
+                const double ca = B.Dhat[a * PP + l], cb = B.Dhat[bb * PP + l];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    ga[c] += ca * wfp[c * NF + l + PP * bb];
+                    gb[c] += cb * wfp[c * NF + a + PP * l];
+                }
+            }
+            const double* ef = edge + f * 16 * PP;       // [u][side][c][PP]
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                ga[c] = ph.s * (B.bpw[a] * ef[(4 + c) * PP + bb] - B.bmw[a] * ef[c * PP + bb] - ga[c]);
+                gb[c] = ph.s * (B.bpw[bb] * ef[(12 + c) * PP + a] - B.bmw[bb] * ef[(8 + c) * PP + a] - gb[c]);
+            }
+            // back to the element's axes: the normal is d, the face's first
+            // axis the lower of the other two
+            double gf[3][4];
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const bool first = (x == 0 && d != 0) || (x == 1 && d == 0);
+                    gf[x][c] = x == d ? gn[c] : (first ? ga[c] : gb[c]);
+                }
+            const double v[3] = {fq[r][1], fq[r][2], fq[r][3]};
+            double Fv[4];
+            flux_viscous_rot(d, fq[r][0], v, gf, ph, Fv);
+            double* o = D.fv + (size_t)(e * 6 + f) * 4 * NF + fn;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o[c * NF] = Fv[c];
+        }
+    }
+}
+
+// BR1 pass: one-sided viscous normal fluxes on the six faces of each
+// element.  The face form does less arithmetic but more index work per face
+// node; measured, it is the faster one at P = 8 only.
+template <int PP>
+__global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::GRAD_WPE)))
+k_grad(DescList dl) {
+    if constexpr (PP >= 9) grad_face_form<PP>(dl);
+    else grad_volume_form<PP>(dl);
 }
 
 // Residual (update == 0: out = p(q) + forcing) or Runge-Kutta stage

@@ -27,6 +27,12 @@ struct BasisTab {
     double bm[kMaxPP];
     double bpw[kMaxPP];
     double bmw[kMaxPP];
+    // the weak derivative along a line evaluated at the line's minus (0) and
+    // plus (1) end: dface[s][l] = sum_m b_s(m) Dhat[m][l] and the lifting
+    // weights lface_p[s] = sum_m b_s(m) b+_m/w_m, lface_m[s] = sum_m b_s(m) b-_m/w_m
+    double dface[2][kMaxPP];
+    double lface_p[2];
+    double lface_m[2];
 };
 
 // Per-solve physical constants, in the form the kernels use them.
