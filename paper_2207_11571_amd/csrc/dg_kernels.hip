@@ -11,8 +11,9 @@
 //
 // Per Runge-Kutta stage two kernels run (BR1 needs neighbours' gradients,
 // which need their neighbours' traces):
-//   k_grad  : q, neighbour q traces -> BR1 gradient -> one-sided viscous
-//             normal flux on the element's six faces (fv);
+//   k_grad  : q, neighbour q traces -> BR1 gradient (at P = 8 only its
+//             face values) -> one-sided viscous normal flux on the element's
+//             six faces (fv);
 //   k_resid : q, neighbour q traces, fv of both sides -> Roe minus averaged
 //             viscous interface flux, volume flux divergence, forcing ->
 //             residual, or the low-storage stage update of q and k plus the
