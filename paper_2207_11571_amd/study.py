@@ -62,11 +62,16 @@ def variant(name, target="eq5", io="all", act="tanh", mode="stage", epochs=30, l
 
 class Reference:
     """A P = 8 Taylor-Green run from t = 0 at one Reynolds number, advanced on
-    demand with a fixed step (from the initial state: dT / n_hi)."""
+    demand with a fixed step (from the initial state: dT / n_hi).  cs_hi /
+    cs_lo: Smagorinsky constants of the high-order scheme (and of the plain
+    higher orders compared with it) and of the low-order scheme, 0 for none
+    (Table 1 case 3: LES in the high order; 3b without, 3c with LES in the
+    corrected low order)."""
 
-    def __init__(self, N, Re, dT, P_lo, cfl=0.4):
+    def __init__(self, N, Re, dT, P_lo, cfl=0.4, cs_hi=0.0, cs_lo=0.0):
         self.N, self.Re, self.dT, self.P_lo = N, Re, dT, P_lo
-        self.m_hi, self.m_lo = B.Mesh(N, P_HO, Re), B.Mesh(N, P_lo, Re)
+        self.cs_hi, self.cs_lo = cs_hi, cs_lo
+        self.m_hi, self.m_lo = B.Mesh(N, P_HO, Re, Cs=cs_hi), B.Mesh(N, P_lo, Re, Cs=cs_lo)
         self.q = self.m_hi.field()
         B.dg_init_tgv(self.m_hi, self.q)
         q_lo = self.m_lo.field()
@@ -116,7 +121,7 @@ class Reference:
         ref = torch.empty((n_eval + 1, 5, E, n_p), dtype=torch.float64, device="cuda")
         init = {}
         for P in orders:
-            m = B.Mesh(self.N, P, self.Re)
+            m = B.Mesh(self.N, P, self.Re, Cs=self.cs_hi)
             f = m.field()
             B.dg_project(m_hi, m, self.q, f)
             init[P] = (m, f)
@@ -240,21 +245,23 @@ def _gain(base, run):
 
 
 def run_study(N=16, Re=1600.0, t0=4.0, window=1.0, snapshots=50, eval_end=5.5, epochs=30, batch=4096,
-              lr=1e-3, seed=0, orders=(4, 5, 6), cfl=0.4, log=print, variants=None, P_lo=3):
+              lr=1e-3, seed=0, orders=(4, 5, 6), cfl=0.4, log=print, variants=None, P_lo=3, cs_hi=0.0, cs_lo=0.0):
     """One time frame.  variants: list of ``variant(...)`` dicts (or (name,
     mask, epochs, lr) tuples: Eq. (5) pairs, all variables, tanh, every
-    stage); default one such variant from the arguments."""
+    stage); default one such variant from the arguments.  cs_hi, cs_lo: the
+    Smagorinsky constants of the high- and low-order schemes (0: none)."""
     if variants is None:
         variants = [variant("nn", epochs=epochs, lr=lr)]
     variants = [v if isinstance(v, dict) else variant(v[0], mask=v[1], epochs=v[2], lr=v[3]) for v in variants]
     targets = sorted({v["target"] for v in variants})
     out = {"config": dict(N=N, Re=Re, t0=t0, window=window, snapshots=snapshots, eval_end=eval_end, P_lo=P_lo,
-                          batch=batch, seed=seed, orders=list(orders), variants=variants)}
+                          batch=batch, seed=seed, orders=list(orders), variants=variants, cs_hi=cs_hi,
+                          cs_lo=cs_lo)}
     dT = window / snapshots
     n_eval = int(round((eval_end - t0) / dT))
     lo = f"P{P_lo}"
 
-    ref = Reference(N, Re, dT, P_lo, cfl)
+    ref = Reference(N, Re, dT, P_lo, cfl, cs_hi, cs_lo)
     ref.advance_to(t0)
     t_ref = ref.seconds
     log(f"P{P_HO} reached t0={t0} in {t_ref:.2f}s (dt={ref.dt_hi:.4e})")
@@ -467,6 +474,8 @@ def main():
     ap.add_argument("--online", default=None, help="t0,t_end: online retraining loop instead of one frame")
     ap.add_argument("--tol", type=float, default=1e-2)
     ap.add_argument("--eval-span", type=float, default=0.3)
+    ap.add_argument("--cs-hi", type=float, default=0.0, help="Smagorinsky constant of the high order (0: none)")
+    ap.add_argument("--cs-lo", type=float, default=0.0, help="Smagorinsky constant of the low order (0: none)")
     a = ap.parse_args()
     torch.cuda.set_device(0)
     log = lambda *x: print("[study]", *x, flush=True)
@@ -487,7 +496,8 @@ def main():
     else:
         res = run_study(N=a.N, Re=a.Re, t0=a.t0, window=a.window, snapshots=a.snapshots, eval_end=a.eval_end,
                         epochs=a.epochs, batch=a.batch, lr=a.lr, orders=tuple(int(x) for x in a.orders.split(",")),
-                        log=log, variants=_variants(a.variants) if a.variants else None, P_lo=a.P_lo)
+                        log=log, variants=_variants(a.variants) if a.variants else None, P_lo=a.P_lo,
+                        cs_hi=a.cs_hi, cs_lo=a.cs_lo)
         summary = {"gain": res["gain"], "comparison": res["comparison"]}
     if a.out:
         open(a.out, "w").write(json.dumps(res))

@@ -2,6 +2,8 @@
 at P_LO = 2 and 3, Re 30 and 200, time frame t = 10, on the paper's mesh
 (8^3 elements, P_HO = 8, window 0.15, evaluation over 0.45).  The network is
 Algorithm 1's all-variable form (pairs and correction after each step).
+Case 3 (Re 1600, t = 7, Smagorinsky closure in the high order, with and
+without it in the corrected low order) uses the paper's network form.
 
 Parity unpinned (the paper's error figures are not available): the checks
 are the project's own accuracy ordering against plain higher orders.
@@ -44,3 +46,28 @@ def test_p3_with_forcing_near_p6_at_re200():
     assert r["P3+alg1a"]["mean_e_window"] < 0.1 * r["P3"]["mean_e_window"]
     assert r["P3+alg1a"]["mean_e_window"] < 1.5 * r["P6"]["mean_e_window"]
     assert r["P3+alg1a"]["wall_s"] < r["P6"]["wall_s"]
+
+
+def test_case3_les_reference_with_and_without_les_in_the_low_order():
+    """Table 1 case 3 at t = 7: the P = 8 reference runs the Smagorinsky
+    closure (Cs = 0.1); the corrected P = 3 run (the paper's network form:
+    Algorithm 1 pairs and correction, momenta, relu) runs without (3b) and
+    with (3c) the closure.  Both must gain clearly over their uncorrected
+    low order inside the window."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_11571_amd import study as st
+    runs = {}
+    for cs_lo in (0.0, 0.1):
+        say("case 3, low-order Cs", cs_lo)
+        res = st.run_study(N=8, Re=1600.0, t0=7.0, window=0.15, snapshots=100, eval_end=7.45, batch=512, orders=(),
+                           P_lo=3, cs_hi=0.1, cs_lo=cs_lo,
+                           variants=[st.variant("alg1", "alg1", "momentum", "relu", "post", epochs=200)],
+                           log=lambda *a: print("[study]", *a, flush=True))
+        runs[cs_lo] = res["runs"]
+    for cs_lo, r in runs.items():
+        print("low-order Cs %.1f: mean e window P3 %.3e P3+NN %.3e; after P3 %.3e P3+NN %.3e" % (
+            cs_lo, r["P3"]["mean_e_window"], r["P3+alg1"]["mean_e_window"], r["P3"]["mean_e_beyond"],
+            r["P3+alg1"]["mean_e_beyond"]))
+        assert r["P3+alg1"]["mean_e_window"] < 0.6 * r["P3"]["mean_e_window"]
+        assert r["P3+alg1"]["mean_e_beyond"] < r["P3"]["mean_e_beyond"]
