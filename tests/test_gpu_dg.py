@@ -168,6 +168,45 @@ def test_rk_full_size_conservation_and_determinism(B):
     assert d1[0] < d0[0]    # kinetic energy decays
 
 
+@pytest.mark.parametrize("P", [3, 6, 8])
+def test_profiled_steps_equal_plain_steps(B, P):
+    """The measurement twin runs the same launches: the state after profiled
+    steps is bitwise the state after plain steps, and every stage kernel
+    reports a positive mean duration (the network's is 0 without a model)."""
+    say("profiled steps", P)
+    m = B.Mesh(8, P, 1600.0)
+    q = m.field()
+    B.dg_init_tgv(m, q)
+    dt = B.dg_stable_dt(m, q)
+    q2 = q.clone()
+    k, k2 = m.field(0.0), m.field(0.0)
+    B.dg_rk_step(m, q, k, dt, 3)
+    prof = B.dg_profile_steps(m, q2, k2, dt, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(q, q2) and torch.equal(k, k2)
+    assert prof["traces"] > 0 and prof["grad"] > 0 and prof["resid"] > 0 and prof["net"] == 0
+
+
+def test_profiled_corrected_steps_equal_plain_steps(B):
+    """The same with the forcing network at every stage (P = 3)."""
+    say("profiled corrected steps")
+    dims = [320, 256, 256, 256, 320]
+    norm = [1.0, 0.0, 0.0, 0.0, synthetic.TGV_ENERGY_LEVEL, 0.01, 1.0, 1.0, 1.0, 1.0,
+            0.0, 0.0, 0.0, 0.0, 0.0, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3]
+    model = B.Model(dims, B.pack_params(synthetic.mlp_init(dims, seed=0)), norm, train=False)
+    m = B.Mesh(8, 3, 200.0)
+    q = m.field()
+    B.dg_init_tgv(m, q)
+    dt = B.dg_stable_dt(m, q)
+    q2 = q.clone()
+    k, k2 = m.field(0.0), m.field(0.0)
+    B.dg_rk_step(m, q, k, dt, 3, model=model)
+    prof = B.dg_profile_steps(m, q2, k2, dt, 3, model=model)
+    torch.cuda.synchronize()
+    assert torch.equal(q, q2) and torch.equal(k, k2)
+    assert prof["net"] > 0 and prof["grad"] > 0 and prof["resid"] > 0
+
+
 def test_diagnostics_and_error_norm(B):
     dg, forcing, projection, rk = _oracle()
     say("diagnostics")
