@@ -128,24 +128,36 @@ def test_invalid_requests(B):
     srv.close()
 
 
-@pytest.mark.parametrize("after_step", [False, True])
-def test_server_solve_equals_library_stepping(B, model, after_step):
-    """A corrected solve run by the server (forcing at every stage, or
-    Algorithm 1's correction after each step) ends in the same state as the
-    library's own stepper with the same time step, bitwise."""
-    say("serving vs library stepping", after_step)
-    N, P, Re, t_end = 4, 3, 200.0, 0.03
+SERVED = {"P3 forcing every stage": dict(Re=200.0, P=3, N=4, Cs=0.0, use_nn=True, after_step=False, t_end=0.03),
+          "P3 correction after each step": dict(Re=200.0, P=3, N=4, Cs=0.0, use_nn=True, after_step=True,
+                                                t_end=0.03),
+          "P6 plain": dict(Re=1600.0, P=6, N=3, Cs=0.0, use_nn=False, after_step=False, t_end=0.005),
+          "P8 plain with the closure": dict(Re=1600.0, P=8, N=2, Cs=0.1, use_nn=False, after_step=False,
+                                            t_end=0.003)}
+
+
+@pytest.mark.parametrize("case", list(SERVED))
+def test_server_solve_equals_library_stepping(B, model, case):
+    """A solve run by the server (plain, forcing at every stage, or Algorithm
+    1's correction after each step) ends in the same state as the library's
+    own stepper with the same time step, bitwise."""
+    c = SERVED[case]
+    say("serving vs library stepping", case)
     srv = B.Server(256 << 20, max_slots=4)
-    rid = srv.submit(Re=Re, P=P, N=N, t_end=t_end, use_nn=True, model=model, want_state=True, after_step=after_step)
+    kw = dict(use_nn=True, model=model, after_step=c["after_step"]) if c["use_nn"] else {}
+    if c["Cs"]:
+        kw["Cs"] = c["Cs"]
+    rid = srv.submit(Re=c["Re"], P=c["P"], N=c["N"], t_end=c["t_end"], want_state=True, **kw)
     st = _wait(srv, [rid])[rid]
     assert st.state == B.SOLVE_DONE, st.error
     _, q_srv = srv.results(rid)
     srv.close()
-    m = B.Mesh(N, P, Re)
+    m = B.Mesh(c["N"], c["P"], c["Re"], Cs=c["Cs"])
     q = m.field()
     B.dg_init_tgv(m, q)
     k = m.field(0.0)
-    assert st.n_steps >= 1 and abs(st.dt * st.n_steps - t_end) < 1e-12
-    (B.dg_rk_step_post if after_step else B.dg_rk_step)(m, q, k, st.dt, st.n_steps, model=model)
+    assert st.n_steps >= 1 and abs(st.dt * st.n_steps - c["t_end"]) < 1e-12
+    step = B.dg_rk_step_post if c["after_step"] else B.dg_rk_step
+    step(m, q, k, st.dt, st.n_steps, model=model if c["use_nn"] else None)
     torch.cuda.synchronize()
     assert np.array_equal(q.cpu().numpy().ravel(), q_srv)
