@@ -229,8 +229,8 @@ def counter_traffic(kernel_file, tag):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
-                                   "(the multi-GPU sharding is a design, see the design notes)"}))
+        print(json.dumps({"error": "the library runs one solve on one GPU: --gpus must be 1 "
+                                   "(sharding a solve over several GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     import synthetic

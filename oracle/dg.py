@@ -23,7 +23,7 @@ element axes followed by three node axes (i along x).  The flat layout used at
 the library boundary, ``q[v][e][n]`` with e = ex + N (ey + N ez) and
 n = i + (P+1)(j + (P+1) k), is exactly this array reshaped.
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
 gamma = 1.4, Pr = 0.72, mu = 1/Re constant, T == p/rho (so kappa = mu gamma /
 ((gamma-1) Pr)), Smagorinsky filter width h/(P+1) and Pr_t = 0.6, no entropy
 fix in the Roe solver, BR1 common value = mean of the primitive variables

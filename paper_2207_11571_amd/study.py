@@ -353,7 +353,7 @@ def run_online(N=8, Re=200.0, P_lo=3, t0=4.0, t_end=7.0, window=0.15, snapshots=
                retrain_snapshots=50, tol=1e-2, max_retrains=50, net=None, retrain_epochs=50, batch=512, seed=0,
                cfl=0.4, log=print):
     """The online retraining loop the paper proposes as future work (Sec. 4):
-    a P = 8 shadow run supplies the error judge; the corrected low-order run
+    a P = 8 shadow run supplies the reference for the error; the corrected low-order run
     starts from the filtered P = 8 state at the end of the first training
     window, and whenever its error e_n exceeds `tol`, the shadow's next
     `retrain_window` produces fresh pairs, the network is retrained from its

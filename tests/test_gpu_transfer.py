@@ -47,11 +47,11 @@ def test_retraining_reaches_scratch_accuracy_faster(transfer):
 
 
 def test_online_retraining_loop():
-    """The retraining loop of the paper's outlook: a P = 8 shadow run judges
-    the corrected P = 3 run at Re 200 from t = 4 to 7; whenever e_n exceeds
-    the tolerance the network is retrained from its current weights on a
-    fresh 0.075-long window and the low order is re-matched to the filtered
-    P = 8 state.  Retraining must beat re-matching alone, the first network
+    """The retraining loop of the paper's outlook: a P = 8 shadow run
+    measures the error of the corrected P = 3 run at Re 200 from t = 4 to 7;
+    whenever e_n exceeds the tolerance the network is retrained from its
+    current weights on a fresh 0.075-long window and the low order is
+    re-matched to the filtered P = 8 state.  Retraining must beat re-matching alone, the first network
     alone and the uncorrected low order, and keep e_n near the tolerance."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

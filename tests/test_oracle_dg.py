@@ -208,7 +208,7 @@ def _sym_tgv_residual(Re, Mach, gamma=1.4, Pr=0.72):
 
 
 def test_tgv_momentum_closed_form():
-    """The survey-independent incompressible closed form of d(rho u)/dt at t = 0:
+    """An independent, incompressible closed form of d(rho u)/dt at t = 0:
     -1/8 sin 2x cos 2z - (3/Re) sin x cos y cos z (and its mirror for rho v)."""
     Re = 200.0
     errs = []
