@@ -297,3 +297,87 @@ def test_per_node_normalisation_forcing_and_gradients(B):
         eW, eb = rel_l2(gW, rW), rel_l2(gb, rb)
         print("layer", l, "grad rel L2", eW, eb)
         assert eW < 1e-2 and eb < 1e-2
+
+
+def test_momentum_network_P2_forcing_and_gradients(B):
+    """The paper's network form at P_LO = 2 (Table 1, 1a - 2b): the three
+    momenta in and out, 81 -> 256 x 3 relu -> 81 (the device pads 81 to 96).
+    Forcing against the oracle, and one training step's gradients against the
+    oracle with bfloat16-stored activations (the gate); the distance from the
+    unquantised float64 oracle is reported beside it and bounded loosely
+    (relu's derivative decisions can differ where an activation rounds across
+    zero)."""
+    from oracle import dg, forcing, mlp
+    say("momentum network P2")
+    dims = [81, 256, 256, 256, 81]
+    layers = synthetic.mlp_init(dims, seed=5)
+    layers = [(W, b + 0.01) for W, b in layers]
+    params, norm = _oracle_model(layers)
+    prm, q = _state(4, 2, 30.0, seed=9)
+    qf = dg.to_flat(q)
+    ref = forcing.network_forcing(qf, params, norm, "relu", MOM, MOM)
+    m = B.Mesh(4, 2, 30.0)
+    model = B.Model(dims, B.pack_params(layers), NORM, activation="relu", in_vars=MOM, out_vars=MOM)
+    out = m.field(0.0)
+    B.nn_forcing(model, m, _to_gpu(qf), out)
+    got = out.cpu().numpy()
+    err = rel_l2(got, ref)
+    print("P2 momentum forcing rel L2", err)
+    assert err < 1e-2 and not got[[0, 4]].any()
+    batch, n_p = 256, 27
+    rng = np.random.default_rng(10)
+    x = np.empty((batch, 135), dtype=np.float32)
+    x[:, :27] = 1.0 + 0.01 * rng.standard_normal((batch, 27))
+    x[:, 27:108] = rng.standard_normal((batch, 81))
+    x[:, 108:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((batch, 27))
+    y = (1e-2 * rng.standard_normal((batch, 135))).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    B.nn_train_step(model, _to_gpu(x, np.float32), _to_gpu(y, np.float32), lr=1e-3, loss=loss)
+    torch.cuda.synchronize()
+    mi, si = np.repeat(norm.mu_in[list(MOM)], n_p), np.repeat(norm.sigma_in[list(MOM)], n_p)
+    mo, so = np.repeat(norm.mu_out[list(MOM)], n_p), np.repeat(norm.sigma_out[list(MOM)], n_p)
+    xh = (x[:, 27:108].astype(np.float64) - mi) / si
+    yt = (y[:, 27:108].astype(np.float64) - mo) / so
+    loss_q, grads_q = mlp.mse_loss_and_grads(params, xh, yt, "relu", quantise=True)
+    _, grads_f = mlp.mse_loss_and_grads(params, xh, yt, "relu", quantise=False)
+    assert abs(loss.item() / loss_q - 1) < 1e-2
+    g_gpu = B.unpack_params(model.grad.cpu().numpy().astype(np.float64), dims)
+    for l, ((gW, gb), (qW, qb), (fW, fb)) in enumerate(zip(g_gpu, grads_q, grads_f)):
+        eq, ef = max(rel_l2(gW, qW), rel_l2(gb, qb)), max(rel_l2(gW, fW), rel_l2(gb, fb))
+        print("P2 momentum layer", l, "grad rel L2 vs bf16-activation oracle", eq, "vs float64 oracle", ef)
+        assert eq < 1e-2
+        assert ef < 1e-1
+
+
+def test_momentum_network_unquantised_gradient_error(B):
+    """The P = 3 momentum relu network of the other tests: the distance of
+    the device gradient from the unquantised float64 oracle, reported per
+    layer (the gated comparison is the bfloat16-activation one)."""
+    from oracle import mlp
+    say("momentum network unquantised gradient error")
+    layers = synthetic.mlp_init(DIMS, seed=3)
+    layers = [(W, b + 0.01) for W, b in layers]
+    params, norm = _oracle_model(layers)
+    model = B.Model(DIMS, B.pack_params(layers), NORM, activation="relu", in_vars=MOM, out_vars=MOM)
+    batch, n_p = 256, 64
+    rng = np.random.default_rng(7)
+    x = np.empty((batch, 320), dtype=np.float32)
+    x[:, :64] = 1.0 + 0.01 * rng.standard_normal((batch, 64))
+    x[:, 64:256] = rng.standard_normal((batch, 192))
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((batch, 64))
+    y = (1e-2 * rng.standard_normal((batch, 320))).astype(np.float32)
+    B.nn_train_step(model, _to_gpu(x, np.float32), _to_gpu(y, np.float32), lr=1e-3)
+    torch.cuda.synchronize()
+    mi, si = np.repeat(norm.mu_in[list(MOM)], n_p), np.repeat(norm.sigma_in[list(MOM)], n_p)
+    mo, so = np.repeat(norm.mu_out[list(MOM)], n_p), np.repeat(norm.sigma_out[list(MOM)], n_p)
+    xh = (x[:, 64:256].astype(np.float64) - mi) / si
+    yt = (y[:, 64:256].astype(np.float64) - mo) / so
+    _, grads_f = mlp.mse_loss_and_grads(params, xh, yt, "relu", quantise=False)
+    _, grads_q = mlp.mse_loss_and_grads(params, xh, yt, "relu", quantise=True)
+    g_gpu = B.unpack_params(model.grad.cpu().numpy().astype(np.float64), DIMS)
+    worst = 0.0
+    for l, ((gW, gb), (qW, qb), (fW, fb)) in enumerate(zip(g_gpu, grads_q, grads_f)):
+        eq, ef = max(rel_l2(gW, qW), rel_l2(gb, qb)), max(rel_l2(gW, fW), rel_l2(gb, fb))
+        print("P3 momentum layer", l, "grad rel L2 vs bf16-activation oracle", eq, "vs float64 oracle", ef)
+        worst = max(worst, ef)
+    assert worst < 1e-1

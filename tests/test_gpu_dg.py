@@ -82,7 +82,7 @@ def test_residual_random_states(B, N, P, Cs, viscous):
     assert np.all(l2 < 1e-12) and np.all(li < 1e-11)
 
 
-@pytest.mark.parametrize("P,Cs", [(8, 0.0), (8, 0.1), (6, 0.1)])
+@pytest.mark.parametrize("P,Cs", [(6, 0.0), (8, 0.0), (8, 0.1), (6, 0.1)])
 def test_residual_full_size_sampled(B, P, Cs):
     """16^3 elements at Re 1600 (the throughput configuration): the residual of
     a perturbed TGV state on sampled elements, each checked against the oracle
@@ -106,6 +106,42 @@ def test_residual_full_size_sampled(B, P, Cs):
         got = Rb[:, centre[0], centre[1], centre[2]]
         l2, li = field_parity(got, ref, 1e-12)
         assert np.all(l2 < 1e-12) and np.all(li < 1e-11), (centre, l2, li)
+
+
+def test_residual_C1_against_extended_precision(B):
+    """The device residual of the 4^3, P = 3, Re 30 Taylor-Green state against
+    the oracle evaluated in 80-bit extended precision (basis tables and
+    constants too): within max(1e-12, 4 x the FP64 oracle's own distance from
+    it) per variable."""
+    import test_oracle_pins as pins
+    dg, *_ = _oracle()
+    say("residual C1 vs extended precision")
+    prm = dg.Params(N=4, P=3, Re=30.0)
+    q = dg.tgv_initial_condition(prm)
+    floor, Rld = pins.roundoff_floor(q, prm)
+    got, _ = _residual_case(B, 4, 3, 30.0, 0.0, True, dg.to_flat(q))
+    ref = np.asarray(Rld, dtype=np.longdouble).reshape(5, -1)
+    got = np.asarray(got, dtype=np.longdouble).reshape(5, -1)
+    err = np.asarray(np.sqrt(np.sum((got - ref) ** 2, axis=1)) / np.sqrt(np.sum(ref ** 2, axis=1)), dtype=np.float64)
+    print("device vs extended precision", err, "FP64 oracle floor", floor)
+    assert np.all(err <= np.maximum(1e-12, 4.0 * floor)), (err, floor)
+
+
+def test_stable_dt_viscous_branch(B):
+    """Re = 1 on 4^3 elements: the viscous bound of Eq. (7) binds; the device
+    value equals the oracle's (and its closed form)."""
+    dg, *_ = _oracle()
+    say("stable dt viscous")
+    for N, P, Re in ((4, 3, 1.0), (4, 5, 0.5)):
+        prm = dg.Params(N=N, P=P, Re=Re)
+        q0 = dg.tgv_initial_condition(prm)
+        ref = dg.stable_dt(q0, prm)
+        closed = 0.4 * prm.h ** 2 / ((P + 1) ** 4 * prm.gamma * prm.mu / prm.Pr)
+        assert abs(ref / closed - 1) < 1e-14
+        m = B.Mesh(N, P, Re)
+        q = _to_gpu(dg.to_flat(q0))
+        dt = B.dg_stable_dt(m, q)
+        assert abs(dt / ref - 1) < 1e-14, (N, P, Re, dt, ref)
 
 
 def test_rk_steps_C1(B):

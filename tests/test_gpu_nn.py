@@ -219,3 +219,126 @@ def test_train_step_row_indices(B):
     B.nn_train_step(m2, _to_gpu(x[idx], np.float32), _to_gpu(y[idx], np.float32))
     torch.cuda.synchronize()
     assert torch.equal(m1.params, m2.params) and torch.equal(m1.grad, m2.grad)
+
+
+def test_corrected_ke_history_C3(B):
+    """The corrected run at its throughput size: 16^3 elements, P = 3, Re 200,
+    the Gaussian network at every stage, 100 steps.  The kinetic energy after
+    every step matches the oracle's history (tests/golden/c3_ke_history.json,
+    written by the committed oracle-only script beside it) to 1e-3."""
+    import json
+    import os
+    from oracle import dg
+    say("corrected KE history C3 16^3")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_ke_history.json")))
+    assert gold["dims"] == DIMS and gold["norm"] == NORM
+    N, P, Re = gold["N"], gold["P"], gold["Re"]
+    m = B.Mesh(N, P, Re)
+    q = m.field()
+    B.dg_init_tgv(m, q)
+    dt = B.dg_stable_dt(m, q)
+    assert abs(dt / gold["dt"] - 1) < 1e-13
+    model = B.Model(DIMS, B.pack_params(synthetic.mlp_init(DIMS, seed=gold["seed"])), NORM, train=False)
+    k = m.field(0.0)
+    ke = []
+    for n in range(len(gold["ke"])):
+        B.dg_rk_step(m, q, k, dt, 1, model=model)
+        ke.append(B.dg_diagnostics(m, q)[0].item())
+    ke, ke_ref = np.array(ke), np.array(gold["ke"])
+    err = np.max(np.abs(ke - ke_ref) / ke_ref)
+    print("C3 KE history max rel", err)
+    assert err < 1e-3
+
+
+def test_adam_several_steps(B):
+    """Four Adam steps on fixed data: after each, the device's float32 master
+    weights equal the float64 Adam recursion (Kingma-Ba with bias correction,
+    beta = (0.9, 0.999), eps = 1e-7) driven by the device's own gradients,
+    and the fourth step's gradient matches the oracle's at the device's
+    current weights.  From step 2 on, swapped or mis-corrected moments change
+    the update by ~1e-4 of a weight, far above the 1e-6 tolerance."""
+    from oracle import mlp
+    say("adam several steps")
+    dims = DIMS
+    layers = synthetic.mlp_init(dims, seed=1)
+    layers = [(W, b + 0.01) for W, b in layers]
+    rng = np.random.default_rng(12)
+    batch = 256
+    x = np.empty((batch, 320), dtype=np.float32)
+    x[:, :64] = 1.0 + 0.01 * rng.standard_normal((batch, 64))
+    x[:, 64:256] = rng.standard_normal((batch, 192))
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((batch, 64))
+    y = (1e-3 * rng.standard_normal((batch, 320))).astype(np.float32)
+    model = B.Model(dims, B.pack_params(layers), NORM)
+    xg, yg = _to_gpu(x, np.float32), _to_gpu(y, np.float32)
+    p_ref = B.unpack_params(model.params.cpu().numpy().astype(np.float64), dims)
+    m_ref, v_ref = mlp.zeros_like_params(p_ref), mlp.zeros_like_params(p_ref)
+    lr = 1e-3
+    for t in range(1, 5):
+        p_dev_before = B.unpack_params(model.params.cpu().numpy().astype(np.float64), dims)
+        B.nn_train_step(model, xg, yg, lr=lr)
+        torch.cuda.synchronize()
+        g_dev = B.unpack_params(model.grad.cpu().numpy().astype(np.float64), dims)
+        p_ref, m_ref, v_ref = mlp.adam_update(p_ref, g_dev, m_ref, v_ref, t, lr=lr)
+        p_dev = B.unpack_params(model.params.cpu().numpy().astype(np.float64), dims)
+        scale = max(np.max(np.abs(W)) for W, _ in p_ref)
+        err = max(max(np.max(np.abs(a - b)) for a, b in zip(pd, pr)) for pd, pr in zip(p_dev, p_ref))
+        moved = max(max(np.max(np.abs(a - b)) for a, b in zip(pd, pb)) for pd, pb in zip(p_dev, p_dev_before))
+        print("adam step", t, "max |dev - ref|", err, "max update", moved)
+        assert err < 1e-6 * scale, (t, err)
+        assert moved > 100 * err
+    # the last step's gradient at the weights the device used for it
+    params, norm = _oracle_model(p_dev_before)
+    n_p = 64
+    xh = (x.astype(np.float64) - np.repeat(norm.mu_in, n_p)) / np.repeat(norm.sigma_in, n_p)
+    yt = (y.astype(np.float64) - np.repeat(norm.mu_out, n_p)) / np.repeat(norm.sigma_out, n_p)
+    _, grads = mlp.mse_loss_and_grads(params, xh, yt)
+    for l, ((gW, gb), (rW, rb)) in enumerate(zip(g_dev, grads)):
+        assert rel_l2(gW, rW) < 1e-2 and rel_l2(gb, rb) < 1e-2, l
+
+
+DIMS_P2 = [135, 256, 256, 256, 135]
+
+
+def test_forcing_and_gradients_P2(B):
+    """The network of the P_LO = 2 cases (Table 1, 1a - 2b): 135 -> 256 x 3
+    tanh -> 135 (five variables x 27 nodes; the device pads 135 to 160).
+    Forcing on a perturbed 4^3 Taylor-Green state and one training step's
+    gradients against the oracle."""
+    from oracle import dg, forcing, mlp
+    say("P2 network forcing and gradients")
+    layers = synthetic.mlp_init(DIMS_P2, seed=4)
+    layers = [(W, b + 0.01) for W, b in layers]
+    params, norm = _oracle_model(layers)
+    prm = dg.Params(N=4, P=2, Re=30.0)
+    q = dg.tgv_initial_condition(prm).copy()
+    q[1:4] += 0.05 * np.random.default_rng(8).standard_normal(q[1:4].shape)
+    qf = dg.to_flat(q)
+    ref = forcing.network_forcing(qf, params, norm)
+    m = B.Mesh(4, 2, 30.0)
+    model = B.Model(DIMS_P2, B.pack_params(layers), NORM)
+    out = m.field(0.0)
+    B.nn_forcing(model, m, _to_gpu(qf), out)
+    torch.cuda.synchronize()
+    err = rel_l2(out.cpu().numpy(), ref)
+    print("P2 forcing rel L2", err)
+    assert err < 1e-2
+    batch, n_p = 200, 27
+    rng = np.random.default_rng(9)
+    x = np.empty((batch, 135), dtype=np.float32)
+    x[:, :27] = 1.0 + 0.01 * rng.standard_normal((batch, 27))
+    x[:, 27:108] = rng.standard_normal((batch, 81))
+    x[:, 108:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((batch, 27))
+    y = (1e-3 * rng.standard_normal((batch, 135))).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    B.nn_train_step(model, _to_gpu(x, np.float32), _to_gpu(y, np.float32), lr=1e-3, loss=loss)
+    torch.cuda.synchronize()
+    xh = (x.astype(np.float64) - np.repeat(norm.mu_in, n_p)) / np.repeat(norm.sigma_in, n_p)
+    yt = (y.astype(np.float64) - np.repeat(norm.mu_out, n_p)) / np.repeat(norm.sigma_out, n_p)
+    loss_ref, grads = mlp.mse_loss_and_grads(params, xh, yt)
+    assert abs(loss.item() / loss_ref - 1) < 1e-2
+    g_gpu = B.unpack_params(model.grad.cpu().numpy().astype(np.float64), DIMS_P2)
+    for l, ((gW, gb), (rW, rb)) in enumerate(zip(g_gpu, grads)):
+        eW, eb = rel_l2(gW, rW), rel_l2(gb, rb)
+        print("P2 layer", l, "grad rel L2", eW, eb)
+        assert eW < 1e-2 and eb < 1e-2

@@ -161,3 +161,57 @@ def test_server_solve_equals_library_stepping(B, model, case):
     step(m, q, k, st.dt, st.n_steps, model=model if c["use_nn"] else None)
     torch.cuda.synchronize()
     assert np.array_equal(q.cpu().numpy().ravel(), q_srv)
+
+
+ORACLE_SERVED = {"P3 with the network at every stage": dict(Re=200.0, P=3, N=4, use_nn=True, t_end=0.03),
+                 "P6 plain": dict(Re=1600.0, P=6, N=4, use_nn=False, t_end=0.006)}
+
+
+@pytest.mark.parametrize("case", list(ORACLE_SERVED))
+def test_served_solve_matches_oracle(B, model, case):
+    """A solve run through solve_submit / solve_poll against the CPU oracle's
+    own integration of the same problem (Taylor-Green state, Eq. (7) step
+    from the initial state, RK3 of Eq. (3) or, with the network, Eq. (4)):
+    final state per variable to 1e-12 relative for the plain solve and 1e-5
+    for the corrected one (its bf16 forcing is ~1e-3 of the residual and
+    agrees to 1e-2), the momenta measured against the momentum vector's norm;
+    kinetic-energy record to 1e-3 (corrected) and 1e-12."""
+    from oracle import dg, forcing, mlp, rk
+    from helpers import state_parity
+    c = ORACLE_SERVED[case]
+    say("served solve vs oracle", case)
+    srv = B.Server(256 << 20, max_slots=4)
+    kw = dict(use_nn=True, model=model) if c["use_nn"] else {}
+    rid = srv.submit(Re=c["Re"], P=c["P"], N=c["N"], t_end=c["t_end"], ke_every=1, ke_capacity=4096,
+                     want_state=True, **kw)
+    st = _wait(srv, [rid])[rid]
+    assert st.state == B.SOLVE_DONE, st.error
+    ke, q_srv = srv.results(rid)
+    ke = ke[:2 * st.ke_count].reshape(-1, 2)
+    srv.close()
+    prm = dg.Params(N=c["N"], P=c["P"], Re=c["Re"])
+    q0 = dg.tgv_initial_condition(prm)
+    n_ref, dt_ref = dg.steps_for(c["t_end"], dg.stable_dt(q0, prm))
+    assert st.n_steps == n_ref and abs(st.dt / dt_ref - 1) < 1e-13
+    if c["use_nn"]:
+        params = [(mlp.bf16_round(W), b.astype(np.float64)) for W, b in synthetic.mlp_init(DIMS, seed=0)]
+        norm = forcing.Normalisation(NORM[0:5], NORM[5:10], NORM[10:15], NORM[15:20])
+        rhs = lambda qq, t: forcing.corrected_rhs(qq, prm, params, norm)
+    else:
+        rhs = lambda qq, t: dg.residual(qq, prm)
+    ke_ref = {0: dg.kinetic_energy(q0, prm)}
+    q_ref = rk.integrate(q0, dt_ref, n_ref, rhs,
+                         callback=lambda n, qq: ke_ref.__setitem__(n, dg.kinetic_energy(qq, prm)))
+    l2, li = state_parity(q_srv, dg.to_flat(q_ref))
+    tol = 1e-5 if c["use_nn"] else 1e-12
+    print(case, "state rel L2", l2, "rel inf", li)
+    assert np.all(l2 < tol) and np.all(li < 10 * tol), (l2, li)
+    assert len(ke) >= n_ref
+    errs = []
+    for t, e in ke:
+        n = int(round(t / dt_ref))
+        assert abs(n * dt_ref - t) < 1e-9 and n in ke_ref
+        errs.append(abs(e - ke_ref[n]) / ke_ref[n])
+    print(case, "KE record max rel", max(errs))
+    assert max(errs) < (1e-3 if c["use_nn"] else 1e-12)
+
