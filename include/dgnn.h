@@ -257,7 +257,19 @@ int nn_data_stats(const float* x, const float* y, int64_t rows, int32_t n_p, dou
  * the caller's arena; the Runge-Kutta stages of all running solves of the
  * same order run in shared launches, so requests that arrive while others run
  * join them at the next step.  Each solve computes exactly what it would
- * compute alone (no cross-solve reductions). */
+ * compute alone (no cross-solve reductions).
+ *
+ * Fallback of the learned part: the uncorrected low-order evolution (Eq. (3),
+ * the base method of Sec. 2.1) backs every corrected solve.  The server
+ * judges a corrected solve's state after every round of steps and at each of
+ * its kinetic-energy records: when a value is not finite, or the kinetic
+ * energy exceeds (1 + 1e-3) times its initial value (the Taylor-Green flow
+ * decays, so the forcing is driving it), the solve returns to the copy of
+ * its state taken at the start of that round (already judged healthy),
+ * drops the records after it and continues uncorrected to t_end.
+ * solve_status reports fallback = 1 and the step it continued from; the
+ * footprint of a corrected solve includes that state copy.  A non-finite
+ * record of an uncorrected solve fails it with DG_ENONFINITE. */
 typedef struct solve_server solve_server;
 
 typedef struct solve_request {
@@ -279,11 +291,12 @@ typedef struct solve_status {
     int32_t error;                  /* DG_* code when failed                       */
     int64_t steps, n_steps;         /* executed / total Runge-Kutta steps          */
     int32_t ke_count;               /* (t, KE) pairs written                       */
-    int32_t reserved;
+    int32_t fallback;               /* 1: a corrected solve continued uncorrected  */
     double t, dt;                   /* physical time reached, step size            */
     double latency_s;               /* completion - submission (done only)         */
     double queue_s;                 /* admission - submission                      */
     int64_t dof_updates;            /* E n_p x executed stages                     */
+    int64_t fallback_step;          /* step it continued uncorrected from, or -1   */
 } solve_status;
 
 /* Bytes a solve of order P on N^3 elements occupies in the arena. */

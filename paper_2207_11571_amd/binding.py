@@ -43,9 +43,9 @@ class solve_request(ctypes.Structure):
 
 class solve_status(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("error", ctypes.c_int32), ("steps", ctypes.c_int64),
-                ("n_steps", ctypes.c_int64), ("ke_count", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_steps", ctypes.c_int64), ("ke_count", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("t", ctypes.c_double), ("dt", ctypes.c_double), ("latency_s", ctypes.c_double),
-                ("queue_s", ctypes.c_double), ("dof_updates", ctypes.c_int64)]
+                ("queue_s", ctypes.c_double), ("dof_updates", ctypes.c_int64), ("fallback_step", ctypes.c_int64)]
 
 
 _vp, _sz, _i32, _i64, _d, _f = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float

@@ -17,6 +17,17 @@
 // alone.  After each round the stream is synchronised once: kinetic-energy
 // records are collected, non-finite solves are failed, finished solves are
 // copied out and their arena blocks released.
+//
+// Fallback of the learned part: a corrected solve (network forcing, Eq. (4),
+// or Algorithm 1's correction) keeps a copy of its state from the start of
+// each round, a state already judged healthy.  At the end of every round its
+// state is judged again (finite diagnostics, kinetic energy not above
+// (1 + kFallbackKeRise) times the initial value -- the Taylor-Green flow
+// decays, so a rise means the forcing is driving it); when that or any of
+// the round's kinetic-energy records fails, the solve returns to the copy,
+// drops the records after it, and continues from there as the uncorrected
+// low-order solve (Eq. (3)), flagged in its status.  A non-finite record of
+// an uncorrected solve fails that solve.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -38,6 +49,7 @@ constexpr int kHist = 64;    // device KE records per solve between synchronisat
 constexpr int kChunk = 16;   // steps per round of the costliest order group
 constexpr int kChunkMax = 256;  // steps per round of any group
 constexpr size_t kDiagDoubles = 8;
+constexpr double kFallbackKeRise = 1e-3;   // relative kinetic-energy rise that ends the correction
 
 static double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -45,10 +57,12 @@ static double now_s() {
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Foot {
-    size_t q, k, ws, desc, hist, total;
+    size_t q, k, ws, desc, hist, health, ckpt, total;
 };
 
-static Foot foot(const Mesh& m) {
+// arena layout of one solve; a corrected solve also holds the state copy of
+// its fallback
+static Foot foot(const Mesh& m, bool corrected) {
     Foot f;
     const size_t field = a256((size_t)5 * m.E * m.n_p * sizeof(double));
     f.q = 0;
@@ -56,7 +70,9 @@ static Foot foot(const Mesh& m) {
     f.ws = 2 * field;
     f.desc = f.ws + a256(ws_layout(m).total);
     f.hist = f.desc + a256(4 * sizeof(SolveDesc));
-    f.total = f.hist + a256(kHist * kDiagDoubles * sizeof(double));
+    f.health = f.hist + a256(kHist * kDiagDoubles * sizeof(double));
+    f.ckpt = f.health + a256(kDiagDoubles * sizeof(double));
+    f.total = f.ckpt + (corrected ? field : 0);
     return f;
 }
 
@@ -93,6 +109,13 @@ struct Solve {
     char* ws = nullptr;
     SolveDesc* ddesc = nullptr;
     double* hist = nullptr;
+    double* health = nullptr;        // diagnostics of the state at the end of a round
+    double* ckpt = nullptr;          // corrected solves: state at the start of the round
+    bool nn_active = false;          // the correction is applied
+    bool fell_back = false;          // continued uncorrected after a failed check
+    int64_t fallback_step = 0;
+    int64_t ckpt_steps = 0;
+    double ke0 = 0.0;
     int par = 0;
     std::vector<double> pending_t;   // times of device records not yet collected
     std::vector<double> ke;          // collected (t, KE) pairs
@@ -172,18 +195,23 @@ static void fail(solve_server* S, Solve* s, int code) {
     S->arena.release(s->off, s->bytes);
 }
 
+static int write_descs(solve_server* S, Solve* s);
+
 // set up one admitted solve: pointers, TGV state, dt, descriptors, traces
 static int admit_one(solve_server* S, Solve* s) {
     const dg_params prm = request_params(s->req);
     int rc = make_mesh(&prm, s->mesh);
     if (rc) return rc;
-    const Foot f = foot(s->mesh);
+    const Foot f = foot(s->mesh, s->req.use_nn != 0);
     char* p = S->base + s->off;
     s->q = (double*)(p + f.q);
     s->k = (double*)(p + f.k);
     s->ws = p + f.ws;
     s->ddesc = (SolveDesc*)(p + f.desc);
     s->hist = (double*)(p + f.hist);
+    s->health = (double*)(p + f.health);
+    s->ckpt = s->req.use_nn ? (double*)(p + f.ckpt) : nullptr;
+    s->nn_active = s->req.use_nn != 0;
     if ((rc = init_tgv_impl(s->mesh, s->q, S->st))) return rc;
     double* dout = s->hist;   // scratch for the time-step diagnostics
     if ((rc = diag_impl(s->mesh, s->q, dout, s->ws, S->st))) return rc;
@@ -193,14 +221,29 @@ static int admit_one(solve_server* S, Solve* s) {
         return set_error(DG_EHIP, "admission readback failed");
     const double dt0 = stable_dt_from_diag(s->mesh, h, 0.4);
     if (!(dt0 > 0) || !std::isfinite(dt0)) return set_error(DG_ENONFINITE, "bad initial state");
+    s->ke0 = h[0];
     s->n_steps = (int64_t)std::ceil(s->req.t_end / dt0 - 1e-12);
     if (s->n_steps < 1) s->n_steps = 1;
     s->dt = s->req.t_end / s->n_steps;
+    if ((rc = write_descs(S, s))) return rc;
+    if (launch_traces(s->mesh.PP, single_list(s->ddesc + 1, s->mesh.E), S->st) != hipSuccess)
+        return set_error(DG_EHIP, "trace launch failed");
+    // record KE(0)
+    if ((rc = diag_impl(s->mesh, s->q, s->hist, s->ws, S->st))) return rc;
+    if (hipStreamSynchronize(S->st) != hipSuccess) return set_error(DG_EHIP, "admission synchronise failed");
+    s->pending_t.push_back(0.0);
+    s->par = 0;
+    s->steps = 0;
+    return DG_OK;
+}
+
+// the four stage descriptors of a solve, with the correction while it is
+// active: d[par] the stages, d[2 + par] the last stage of a step corrected
+// after the step (Algorithm 1), whose update adds dt s(q^n)
+static int write_descs(solve_server* S, Solve* s) {
     const WsLayout L = ws_layout(s->mesh);
-    // d[par]: the stages; d[2 + par]: the last stage of a step corrected after
-    // the step (Algorithm 1), whose update adds dt s(q^n)
-    const bool post = s->req.use_nn && s->req.nn_after_step;
-    const double* fbuf = s->req.use_nn ? (const double*)(s->ws + L.forcing) : nullptr;
+    const bool post = s->nn_active && s->req.nn_after_step;
+    const double* fbuf = s->nn_active ? (const double*)(s->ws + L.forcing) : nullptr;
     SolveDesc d[4];
     for (int p = 0; p < 4; ++p) {
         const int par = p & 1;
@@ -218,14 +261,6 @@ static int admit_one(solve_server* S, Solve* s) {
         d[p].ph = s->mesh.ph;
     }
     if (launch_write_descs(d, 4, s->ddesc, S->st) != hipSuccess) return set_error(DG_EHIP, "descriptor upload failed");
-    if (launch_traces(s->mesh.PP, single_list(s->ddesc + 1, s->mesh.E), S->st) != hipSuccess)
-        return set_error(DG_EHIP, "trace launch failed");
-    // record KE(0)
-    if ((rc = diag_impl(s->mesh, s->q, s->hist, s->ws, S->st))) return rc;
-    if (hipStreamSynchronize(S->st) != hipSuccess) return set_error(DG_EHIP, "admission synchronise failed");
-    s->pending_t.push_back(0.0);
-    s->par = 0;
-    s->steps = 0;
     return DG_OK;
 }
 
@@ -248,7 +283,7 @@ static int step_group(solve_server* S, int PP, std::vector<Solve*>& v, hipStream
             int blk = 0;
             for (size_t i = 0; i < cn; ++i) {
                 Solve* s = v[c0 + i];
-                const bool post = s->req.use_nn && s->req.nn_after_step;
+                const bool post = s->nn_active && s->req.nn_after_step;
                 dl.d[i] = s->ddesc + s->par + ((post && stg == 2) ? 2 : 0);
                 dl.blk[i] = blk;
                 blk += s->mesh.E;
@@ -260,7 +295,7 @@ static int step_group(solve_server* S, int PP, std::vector<Solve*>& v, hipStream
             std::map<const nn_model*, std::vector<NetTarget>> nets;
             for (size_t i = 0; i < cn; ++i) {
                 Solve* s = v[c0 + i];
-                if (!s->req.use_nn) continue;
+                if (!s->nn_active) continue;
                 if (s->req.nn_after_step && stg != 0) continue;   // s(q^n) once, at the step start
                 NetTarget t;
                 t.q = s->q;
@@ -300,7 +335,7 @@ static std::map<int, int64_t> round_plan(const std::map<int, std::vector<Solve*>
     for (auto& g : groups) {
         double c = 0.0;
         for (Solve* s : g.second)
-            c += (double)s->mesh.E * s->mesh.n_p * (s->req.use_nn ? (s->req.nn_after_step ? 1.3 : 2.0) : 1.0);
+            c += (double)s->mesh.E * s->mesh.n_p * (s->nn_active ? (s->req.nn_after_step ? 1.3 : 2.0) : 1.0);
         cost[g.first] = c;
         cmax = std::max(cmax, c);
     }
@@ -317,24 +352,68 @@ static std::map<int, int64_t> round_plan(const std::map<int, std::vector<Solve*>
     return plan;
 }
 
-static void collect(solve_server* S, Solve* s) {
+static bool record_finite(const double* rec) {
+    bool finite = std::isfinite(rec[0]);
+    for (int c = 3; c < 8; ++c) finite = finite && std::isfinite(rec[c]);
+    return finite;
+}
+
+// a corrected solve's state is healthy: finite, kinetic energy not risen
+static bool record_healthy(const Solve* s, const double* rec) {
+    return record_finite(rec) && rec[0] <= s->ke0 * (1.0 + kFallbackKeRise);
+}
+
+// Reads the round's kinetic-energy records (and, for a corrected solve, the
+// end-of-round health record).  Returns true when a corrected solve must
+// fall back: its pending records are then dropped, except those at or
+// before the state copy it returns to.
+static bool collect(solve_server* S, Solve* s) {
     const size_t n = s->pending_t.size();
-    if (n == 0) return;
-    if (hipMemcpy(S->pinned, s->hist, n * kDiagDoubles * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    double health[kDiagDoubles];
+    const bool judge = s->nn_active;
+    if (n > 0 && hipMemcpy(S->pinned, s->hist, n * kDiagDoubles * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
         std::lock_guard<std::mutex> lk(S->mu);
         s->error = DG_EHIP;
-        return;
+        return false;
+    }
+    if (judge && hipMemcpy(health, s->health, sizeof(health), hipMemcpyDeviceToHost) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        s->error = DG_EHIP;
+        return false;
     }
     std::lock_guard<std::mutex> lk(S->mu);
+    bool bad = judge && !record_healthy(s, health);
+    for (size_t r = 0; r < n && judge && !bad; ++r) bad = !record_healthy(s, S->pinned + r * kDiagDoubles);
+    const double t_ckpt = s->ckpt_steps * s->dt;
     for (size_t r = 0; r < n; ++r) {
         const double* rec = S->pinned + r * kDiagDoubles;
-        bool finite = std::isfinite(rec[0]);
-        for (int c = 3; c < 8; ++c) finite = finite && std::isfinite(rec[c]);
-        if (!finite) s->error = DG_ENONFINITE;
+        if (bad && s->pending_t[r] > t_ckpt + 0.5 * s->dt) continue;
+        if (!bad && !record_finite(rec)) s->error = DG_ENONFINITE;
         s->ke.push_back(s->pending_t[r]);
         s->ke.push_back(rec[0]);
     }
     s->pending_t.clear();
+    return bad;
+}
+
+// return a corrected solve to the state copy of the round start and continue
+// it uncorrected from there
+static int fall_back(solve_server* S, Solve* s) {
+    s->nn_active = false;
+    if (hipMemcpyAsync(s->q, s->ckpt, (size_t)5 * s->mesh.E * s->mesh.n_p * sizeof(double), hipMemcpyDeviceToDevice,
+                       S->st) != hipSuccess)
+        return set_error(DG_EHIP, "fallback restore failed");
+    int rc = write_descs(S, s);
+    if (rc) return rc;
+    s->par = 0;
+    if (launch_traces(s->mesh.PP, single_list(s->ddesc + 1, s->mesh.E), S->st) != hipSuccess)
+        return set_error(DG_EHIP, "trace launch failed");
+    if (hipStreamSynchronize(S->st) != hipSuccess) return set_error(DG_EHIP, "fallback synchronise failed");
+    std::lock_guard<std::mutex> lk(S->mu);
+    s->steps = s->ckpt_steps;
+    s->fell_back = true;
+    s->fallback_step = s->ckpt_steps;
+    return DG_OK;
 }
 
 static void finish(solve_server* S, Solve* s) {
@@ -392,7 +471,17 @@ static void server_loop(solve_server* S) {
         for (auto& g : groups) {
             hipStream_t gst = S->gst[g.first];
             const int64_t n_g = plan.at(g.first);
+            // corrected solves: copy of the (already judged) state the round starts from
+            for (Solve* s : g.second)
+                if (s->nn_active && rc == DG_OK) {
+                    s->ckpt_steps = s->steps;
+                    if (hipMemcpyAsync(s->ckpt, s->q, (size_t)5 * s->mesh.E * s->mesh.n_p * sizeof(double),
+                                       hipMemcpyDeviceToDevice, gst) != hipSuccess)
+                        rc = set_error(DG_EHIP, "state copy failed");
+                }
             for (int64_t n = 0; n < n_g && rc == DG_OK; ++n) rc = step_group(S, g.first, g.second, gst);
+            for (Solve* s : g.second)
+                if (s->nn_active && rc == DG_OK) rc = diag_impl(s->mesh, s->q, s->health, s->ws, gst);
             steps_done = std::max(steps_done, n_g);
         }
         for (auto& g : groups) (void)hipStreamSynchronize(S->gst[g.first]);
@@ -404,7 +493,14 @@ static void server_loop(solve_server* S) {
         }
         std::vector<Solve*> keep;
         for (Solve* s : run) {
-            collect(S, s);
+            const bool back = collect(S, s);
+            if (back && rc == DG_OK) {
+                const int frc = fall_back(S, s);
+                if (frc) {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    s->error = frc;
+                }
+            }
             int err;
             {
                 std::lock_guard<std::mutex> lk(S->mu);
@@ -426,7 +522,6 @@ static void server_loop(solve_server* S) {
 extern "C" {
 
 size_t solve_footprint(int32_t P, int32_t N, int32_t use_nn) {
-    (void)use_nn;
     if (P < DG_MIN_ORDER || P > DG_MAX_ORDER || N < 1 || N > 1024) return 0;
     Mesh m;
     std::memset(&m, 0, sizeof(m));
@@ -436,7 +531,7 @@ size_t solve_footprint(int32_t P, int32_t N, int32_t use_nn) {
     m.E = N * N * N;
     m.n_p = m.PP * m.PP * m.PP;
     m.n_f = m.PP * m.PP;
-    return foot(m).total;
+    return foot(m, use_nn != 0).total;
 }
 
 int solve_server_create(void* arena, size_t arena_bytes, int32_t max_slots, solve_server** out) {
@@ -489,7 +584,7 @@ int solve_submit(solve_server* S, const solve_request* r, uint64_t* id) {
         if (!r->model) return set_error(DG_EINVAL, "use_nn without a model");
         if ((rc = net_check_mesh(r->model, m))) return rc;
     }
-    const size_t need = foot(m).total;
+    const size_t need = foot(m, r->use_nn != 0).total;
     if (need > S->bytes) return set_error(DG_ENOSPC, "request needs %zu bytes, arena holds %zu", need, S->bytes);
     auto s = std::make_unique<Solve>();
     s->req = *r;
@@ -520,6 +615,8 @@ int solve_poll(solve_server* S, uint64_t id, solve_status* st) {
     st->steps = s->steps;
     st->n_steps = s->n_steps;
     st->ke_count = (int32_t)std::min((size_t)std::max(0, s->req.ke_capacity), s->ke.size() / 2);
+    st->fallback = s->fell_back ? 1 : 0;
+    st->fallback_step = s->fell_back ? s->fallback_step : -1;
     st->t = s->steps * s->dt;
     st->dt = s->dt;
     st->queue_s = s->state == SOLVE_QUEUED ? 0.0 : s->t_admit - s->t_submit;

@@ -34,7 +34,7 @@ def test_struct_layouts_match_header_sizes():
     from paper_2207_11571_amd import binding
     assert ctypes.sizeof(binding.dg_params) == 16 + 8 * 8
     assert ctypes.sizeof(binding.solve_request) == 4 * 8 + 4 * 4 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(binding.solve_status) == 8 + 16 + 8 + 8 * 4 + 8
+    assert ctypes.sizeof(binding.solve_status) == 8 + 16 + 8 + 8 * 4 + 8 + 8
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -215,3 +215,76 @@ def test_served_solve_matches_oracle(B, model, case):
     print(case, "KE record max rel", max(errs))
     assert max(errs) < (1e-3 if c["use_nn"] else 1e-12)
 
+
+def _served(B, srv, **kw):
+    rid = srv.submit(ke_every=1, ke_capacity=4096, want_state=True, **kw)
+    st = _wait(srv, [rid])[rid]
+    ke, q = srv.results(rid)
+    return st, ke[:2 * st.ke_count].reshape(-1, 2), q
+
+
+def test_fallback_after_blow_up(B):
+    """A network with absurd weights (x20, output scale 10) drives the
+    corrected solve to blow up within its first round of steps: the server
+    returns it to the initial state and finishes it uncorrected, so its
+    final state equals the plain low-order stepping from the Taylor-Green
+    state, bitwise, and its status says so."""
+    say("serving fallback after blow-up")
+    layers = [(20.0 * W, b + 0.5) for W, b in synthetic.mlp_init(DIMS, seed=0)]
+    norm = list(NORM[:15]) + [10.0] * 5
+    bad = B.Model(DIMS, B.pack_params(layers), norm, train=False)
+    srv = B.Server(256 << 20, max_slots=4)
+    st, ke, q_srv = _served(B, srv, Re=200.0, P=3, N=4, t_end=0.05, use_nn=True, model=bad)
+    srv.close()
+    assert st.state == B.SOLVE_DONE, st.error
+    assert st.fallback == 1 and st.fallback_step == 0
+    assert np.all(np.isfinite(q_srv)) and np.all(np.isfinite(ke))
+    m = B.Mesh(4, 3, 200.0)
+    q = m.field()
+    B.dg_init_tgv(m, q)
+    k = m.field(0.0)
+    B.dg_rk_step(m, q, k, st.dt, st.n_steps)
+    torch.cuda.synchronize()
+    assert np.array_equal(q.cpu().numpy().ravel(), q_srv)
+    # the record continues from the initial state with the uncorrected run
+    assert len(ke) == st.n_steps + 1 and np.all(np.diff(ke[:, 0]) > 0)
+
+
+def test_fallback_continues_from_the_last_judged_state(B):
+    """A constant forcing of the x-momentum (0.2 per unit time, from a
+    network whose only non-zero parameters are output biases) adds kinetic
+    energy faster than the Re-200 flow dissipates it: the oracle puts the
+    rise past 1e-3 of the initial value at step 61 on 4^3 elements, P = 3.
+    The server falls back to the copy taken at the start of the round that
+    crossed, and the final state equals the library's corrected stepping up
+    to that step followed by uncorrected stepping to the end, bitwise."""
+    say("serving fallback from a later round")
+    layers = [(0.0 * W, 0.0 * b) for W, b in synthetic.mlp_init(DIMS, seed=0)]
+    layers[-1][1][64:128] = 1.0
+    norm = list(NORM[:15]) + [1e-3, 0.2, 1e-3, 1e-3, 1e-3]
+    drift = B.Model(DIMS, B.pack_params(layers), norm, train=False)
+    srv = B.Server(256 << 20, max_slots=4)
+    st, ke, q_srv = _served(B, srv, Re=200.0, P=3, N=4, t_end=0.4, use_nn=True, model=drift)
+    srv.close()
+    assert st.state == B.SOLVE_DONE, st.error
+    print("fallback from step", st.fallback_step, "of", st.n_steps)
+    assert st.fallback == 1 and 0 < st.fallback_step <= 61
+    m = B.Mesh(4, 3, 200.0)
+    q = m.field()
+    B.dg_init_tgv(m, q)
+    k = m.field(0.0)
+    B.dg_rk_step(m, q, k, st.dt, st.fallback_step, model=drift)
+    B.dg_rk_step(m, q, k, st.dt, st.n_steps - st.fallback_step)
+    torch.cuda.synchronize()
+    assert np.array_equal(q.cpu().numpy().ravel(), q_srv)
+    ke0 = ke[0, 1]
+    assert np.all(ke[:, 1] <= ke0 * (1 + 1e-3))
+    assert len(ke) == st.n_steps + 1
+
+
+def test_healthy_corrected_solve_does_not_fall_back(B, model):
+    say("serving no fallback for a healthy corrected solve")
+    srv = B.Server(256 << 20, max_slots=4)
+    st, ke, _ = _served(B, srv, Re=200.0, P=3, N=4, t_end=0.1, use_nn=True, model=model)
+    srv.close()
+    assert st.state == B.SOLVE_DONE and st.fallback == 0 and st.fallback_step == -1
