@@ -114,6 +114,25 @@ int dg_rk_step(const dg_mesh* m, double* q, double* k, double dt, int32_t n_step
 int dg_rk_step_post(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps,
                     const nn_model* forcing, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dg_rk_step
+ * with the library's own scratch in place of the caller's workspace.  The
+ * scratch is one static device array of DG_NOALLOC_SCRATCH_BYTES per GPU,
+ * created when the code object loads and kept until the process ends; its
+ * address is looked up once per device when the first mesh is built there.
+ * The call allocates nothing (no hipMalloc / hipFree, no library allocator):
+ * the caller passes q and k (same layout and meaning as dg_rk_step) and the
+ * stream.  DG_ENOSPC when the mesh's workspace (dg_mesh_query) is larger
+ * than DG_NOALLOC_SCRATCH_BYTES -- it holds 16^3 elements up to P = 3 and
+ * 8^3 elements up to P = 8.  Every call on one GPU shares that GPU's array
+ * (the last call's face traces, fluxes and forcing stay in it; nothing in it
+ * needs to start at zero): calls that overlap on one GPU, from several
+ * streams or threads, race and must be serialised by the caller.  Other
+ * arguments and errors as dg_rk_step. */
+#define DG_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+int dg_rk_step_noalloc(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps,
+                       const nn_model* forcing, void* stream);
+
 /* Measurement twin of dg_rk_step: the same launches, each bracketed by a HIP
  * event pair on `stream`; out_ms (host, double[4]) receives the mean duration
  * in milliseconds of one launch of each stage kernel: [0] face traces,

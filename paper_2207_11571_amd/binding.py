@@ -60,6 +60,7 @@ SIGNATURES = {
     "dg_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "dg_rk_step": (ctypes.c_int, [_vp, _vp, _vp, _d, _i32, _vp, _vp, _sz, _vp]),
     "dg_rk_step_post": (ctypes.c_int, [_vp, _vp, _vp, _d, _i32, _vp, _vp, _sz, _vp]),
+    "dg_rk_step_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _d, _i32, _vp, _vp]),
     "dg_profile_steps": (ctypes.c_int, [_vp, _vp, _vp, _d, _i32, _vp, _vp, _sz, _vp, ctypes.POINTER(_d)]),
     "dg_diagnostics": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "dg_stable_dt": (ctypes.c_int, [_vp, _vp, _d, ctypes.POINTER(_d), _vp, _sz, _vp]),
@@ -197,6 +198,13 @@ def dg_rk_step_post(mesh, q, k, dt, n_steps, model=None, stream=None):
     check(lib().dg_rk_step_post(mesh.handle, _ptr(q, torch.float64, "q"), _ptr(k, torch.float64, "k"), float(dt),
                                 int(n_steps), model.handle if model is not None else None, _ptr(mesh.ws),
                                 mesh.ws_bytes, _stream(stream)))
+
+
+def dg_rk_step_noalloc(mesh, q, k, dt, n_steps, model=None, stream=None):
+    """dg_rk_step on the library's per-GPU scratch (no workspace argument)."""
+    check(lib().dg_rk_step_noalloc(mesh.handle, _ptr(q, torch.float64, "q"), _ptr(k, torch.float64, "k"),
+                                   float(dt), int(n_steps), model.handle if model is not None else None,
+                                   _stream(stream)))
 
 
 def dg_profile_steps(mesh, q, k, dt, n_steps, model=None, stream=None):

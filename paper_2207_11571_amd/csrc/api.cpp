@@ -141,15 +141,18 @@ static void host_filter(int Ps, int Pd, double* G1) {
 }
 
 static std::mutex g_tab_mu;
-static bool g_tab_done[64];
+static bool g_tab_done[kMaxDevices];
 
+// once per device, with that device current: basis tables and the address
+// of the no-alloc stepper's scratch
 static int ensure_tables(int dev) {
     std::lock_guard<std::mutex> lk(g_tab_mu);
-    if (dev < 0 || dev >= 64) return set_error(DG_EINVAL, "device index %d out of range", dev);
+    if (dev < 0 || dev >= kMaxDevices) return set_error(DG_EINVAL, "device index %d out of range", dev);
     if (g_tab_done[dev]) return DG_OK;
     std::vector<BasisTab> tabs(DG_MAX_ORDER);
     for (int P = 1; P <= DG_MAX_ORDER; ++P) host_basis(P, tabs[P - 1]);
     DG_HIP(upload_basis_tables(tabs.data()));
+    DG_HIP(scratch_setup(dev));
     g_tab_done[dev] = true;
     return DG_OK;
 }
@@ -420,6 +423,25 @@ int dg_rk_step_post(const dg_mesh* m, double* q, double* k, double dt, int32_t n
     if (forcing && (rc = net_check_mesh(forcing, m->m))) return rc;
     if (n_steps == 0) return DG_OK;
     return rk_impl(m->m, q, k, dt, n_steps, forcing, 1, (char*)ws, (hipStream_t)stream);
+}
+
+int dg_rk_step_noalloc(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps, const nn_model* forcing,
+                       void* stream) {
+    int rc = check_mesh(m);
+    if (rc) return rc;
+    if (!q || !k || !aligned8(q) || !aligned8(k)) return set_error(DG_EINVAL, "bad state pointers");
+    if (q == k) return set_error(DG_EINVAL, "q and k alias");
+    if (!(dt > 0) || !std::isfinite(dt)) return set_error(DG_EINVAL, "dt must be positive and finite");
+    if (n_steps < 0) return set_error(DG_EINVAL, "negative step count");
+    const size_t need = ws_layout(m->m).total;
+    if (need > DG_NOALLOC_SCRATCH_BYTES)
+        return set_error(DG_ENOSPC, "N = %d, P = %d needs %zu bytes of workspace; the no-alloc scratch holds %zu",
+                         m->m.N, m->m.P, need, (size_t)DG_NOALLOC_SCRATCH_BYTES);
+    char* ws = (char*)scratch_device_ptr(m->m.device);
+    if (!ws) return set_error(DG_EHIP, "no-alloc scratch not set up on device %d", m->m.device);
+    if (forcing && (rc = net_check_mesh(forcing, m->m))) return rc;
+    if (n_steps == 0) return DG_OK;
+    return rk_impl(m->m, q, k, dt, n_steps, forcing, 0, ws, (hipStream_t)stream);
 }
 
 int dg_profile_steps(const dg_mesh* mh, double* q, double* k, double dt, int32_t n_steps, const nn_model* model,

@@ -18,6 +18,8 @@
 //             viscous interface flux, volume flux divergence, forcing ->
 //             residual, or the low-storage stage update of q and k plus the
 //             face traces of the new q for the next stage.
+#include <mutex>
+
 #include "dgnn_internal.hpp"
 
 namespace dgnn {
@@ -1082,6 +1084,35 @@ __global__ void k_write_descs(DescBatch b, int n, SolveDesc* dev) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         if (threadIdx.x == 0 && i < n) dev[i] = b.d[i];
+}
+
+// ------------------------------------------- scratch of the no-alloc stepper
+
+// Workspace of dg_rk_step_noalloc: one array per GPU, loaded with the code
+// object.  Host code never passes the array's name to a kernel or a copy (on
+// the host it is a stand-in, not a device address); it uses the address that
+// scratch_setup looks up per device.
+static __device__ __align__(256) unsigned char scratch[DG_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+hipError_t scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+    return hipSuccess;
+}
+
+void* scratch_device_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
 }
 
 // ------------------------------------------------------------ host launchers

@@ -14,6 +14,7 @@ namespace dgnn {
 
 constexpr int kMaxPP = DG_MAX_ORDER + 1;   // nodes per direction at the highest order
 constexpr int kMaxLayers = 8;               // weight layers of the forcing network
+constexpr int kMaxDevices = 64;             // GPUs a process can build meshes on
 
 // Gauss-Legendre nodal basis of one order (Sec. 2.6).  D[i*PP + j] = l_j'(xi_i);
 // Dhat[i*PP + m] = D[m][i] w_m / w_i is the weak-form volume operator;
@@ -129,6 +130,10 @@ void fill_phys(const dg_params& p, Phys& ph);
 // ----------------------------------------------------------- host launchers
 // All return hipSuccess or the launch error.  `descs` is device memory.
 hipError_t upload_basis_tables(const BasisTab* host_tabs /* index P-1 */);
+// address of the no-alloc stepper's scratch on device dev (looked up once, by
+// scratch_setup with dev current); null before the set-up
+hipError_t scratch_setup(int dev);
+void* scratch_device_ptr(int dev);
 hipError_t launch_write_descs(const SolveDesc* host, int n, SolveDesc* dev, hipStream_t st);
 hipError_t launch_traces(int PP, const DescList& dl, hipStream_t st);
 hipError_t launch_grad(int PP, const DescList& dl, hipStream_t st);
