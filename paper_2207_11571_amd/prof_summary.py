@@ -3,6 +3,8 @@
     python -m paper_2207_11571_amd.prof_summary trace <dir> "<command>" > profiles/<name>.md
     python -m paper_2207_11571_amd.prof_summary counters <dir> <kernel-substring> <copy-bytes> "<command>"
     python -m paper_2207_11571_amd.prof_summary sq <dir1,dir2,...> "<kernel1;kernel2;...>" "<command>"
+    python -m paper_2207_11571_amd.prof_summary hbm <fetch-dir> <write-dir> <kernel-substring> <copy-bytes> \
+        <algorithmic-bytes> <mean-launch-us> "<command>" > profiles/<kernel>_counters.md
 
 `trace` reads the kernel dispatches of a --kernel-trace run (rocpd SQLite
 database or kernel_stats/kernel_trace CSV) and prints per-kernel count, mean,
@@ -91,6 +93,55 @@ def counters(d, kernel, copy_bytes, command):
     print(f"- bytes per dispatch (scaled): {mean_k * 1024.0 * factor:.0f}")
 
 
+def _counter_mean(d, kernel, cname):
+    """(mean value per dispatch of the kernel, largest value of a copy
+    dispatch) for one counter of a --pmc run."""
+    vals, copies = [], []
+    for name, _, pmc in _dispatches(d):
+        for c, v in pmc.items():
+            if c != cname and not c.startswith(cname):
+                continue
+            if kernel in name:
+                vals.append(v)
+            if "copyBuffer" in name or "copy" in name.lower():
+                copies.append(v)
+    if not vals or not copies:
+        raise SystemExit(f"no {cname} values for {kernel} in {d}")
+    return sum(vals) / len(vals), max(copies), len(vals)
+
+
+def hbm(fetch_dir, write_dir, kernel, copy_bytes, alg_bytes, mean_us, command):
+    """HBM bytes per dispatch of one kernel from a FETCH_SIZE run and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
+    reads for a device copy of copy_bytes, with the sha256 of the kernel
+    source (bench.py uses the figure only while the source is unchanged)."""
+    import hashlib
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = open(os.path.join(root, "paper_2207_11571_amd", "csrc", "dg_kernels.hip"), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    f_k, f_c, n_f = _counter_mean(fetch_dir, kernel, "FETCH_SIZE")
+    w_k, w_c, n_w = _counter_mean(write_dir, kernel, "WRITE_SIZE")
+    ff, fw = copy_bytes / (f_c * 1024.0), copy_bytes / (w_c * 1024.0)
+    fb, wb = f_k * 1024.0 * ff, w_k * 1024.0 * fw
+    tot = fb + wb
+    print(f"# HBM traffic of `{kernel}`\n")
+    print("Two counter runs (FETCH_SIZE, then WRITE_SIZE), each over the same command:\n")
+    print(f"    {command}\n")
+    print(f"Calibration: a device copy of {copy_bytes} bytes reads {f_c:.0f} KiB of FETCH_SIZE (factor {ff:.3f}) "
+          f"and {w_c:.0f} KiB of WRITE_SIZE (factor {fw:.3f}).\n")
+    print("| counter | dispatches | mean KiB / dispatch | factor | bytes / dispatch |")
+    print("|---|---|---|---|---|")
+    print(f"| FETCH_SIZE | {n_f} | {f_k:.1f} | {ff:.3f} | {fb:.0f} |")
+    print(f"| WRITE_SIZE | {n_w} | {w_k:.1f} | {fw:.3f} | {wb:.0f} |\n")
+    print(f"- hbm_bytes_per_launch: {tot:.0f}")
+    print(f"- algorithmic_bytes_per_launch: {alg_bytes:.0f}")
+    print(f"- traffic_over_algorithmic: {tot / alg_bytes:.3f}")
+    print(f"- mean_launch_us: {mean_us:.2f}")
+    print(f"- counter_TBs: {tot / (mean_us * 1e-6) / 1e12:.3f}")
+    print("- source: paper_2207_11571_amd/csrc/dg_kernels.hip")
+    print(f"- source_sha256_16: {sha}")
+
+
 def sq(dirs, kernels, command):
     """Mean per-dispatch SQ counters of the named kernels over several --pmc
     runs (one counter set each), also per wavefront (divided by SQ_WAVES)."""
@@ -123,5 +174,8 @@ if __name__ == "__main__":
         counters(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5])
     elif sys.argv[1] == "sq":
         sq(sys.argv[2].split(","), sys.argv[3].split(";"), sys.argv[4])
+    elif sys.argv[1] == "hbm":
+        hbm(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), float(sys.argv[6]), float(sys.argv[7]),
+            sys.argv[8])
     else:
         raise SystemExit(__doc__)
