@@ -478,12 +478,8 @@ __device__ __forceinline__ void grad_volume_form(const DescList& dl) {
     double qn[5];
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            qn[v] = D.q[((size_t)v * E + e) * NP + t];
-            sh[v * NP + t] = qn[v];
-        }
+        for (int v = 0; v < 5; ++v) qn[v] = D.q[((size_t)v * E + e) * NP + t];
     }
-    __syncthreads();
 
     double fq[S::TPT][4];   // own traced (rho, u, v, w) per face task
 #pragma unroll
@@ -492,7 +488,12 @@ __device__ __forceinline__ void grad_volume_form(const DescList& dl) {
         if (tau < S::NFT) {
             const int f = tau / NF, fn = tau - f * NF;
             double qi[5], qo[5];
-            face_interp<PP, 5>(sh, B, f, fn, qi);
+            // the element's own trace on this face, written with the state
+            // by the trace epilogue (the same line interpolation of the
+            // same values, so the same numbers as interpolating sh here)
+            const double* ti = D.qtr_in + (size_t)(e * 6 + f) * 5 * NF + fn;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qi[v] = ti[v * NF];
             const int nb = neighbour_at(e, D.N, ecx, ecy, ecz, f);
             const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
 #pragma unroll
@@ -508,7 +509,6 @@ __device__ __forceinline__ void grad_volume_form(const DescList& dl) {
             fq[r][3] = wi[2];
         }
     }
-    __syncthreads();
     if (t < NP) {
         double w[4];
         gradient_vars(qn, ph.gm1, w);
@@ -581,12 +581,8 @@ __device__ __forceinline__ void grad_face_form(const DescList& dl) {
     double qn[5];
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            qn[v] = D.q[((size_t)v * E + e) * NP + t];
-            sh[v * NP + t] = qn[v];
-        }
+        for (int v = 0; v < 5; ++v) qn[v] = D.q[((size_t)v * E + e) * NP + t];
     }
-    __syncthreads();
 
     double fq[S::TPT][4];   // own traced (rho, u, v, w) per face task
 #pragma unroll
@@ -595,7 +591,12 @@ __device__ __forceinline__ void grad_face_form(const DescList& dl) {
         if (tau < S::NFT) {
             const int f = tau / NF, fn = tau - f * NF;
             double qi[5], qo[5];
-            face_interp<PP, 5>(sh, B, f, fn, qi);
+            // the element's own trace on this face, written with the state
+            // by the trace epilogue (the same line interpolation of the
+            // same values, so the same numbers as interpolating sh here)
+            const double* ti = D.qtr_in + (size_t)(e * 6 + f) * 5 * NF + fn;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qi[v] = ti[v * NF];
             const int nb = neighbour_at(e, D.N, ecx, ecy, ecz, f);
             const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
 #pragma unroll
@@ -611,13 +612,13 @@ __device__ __forceinline__ void grad_face_form(const DescList& dl) {
             fq[r][3] = wi[2];
         }
     }
-    __syncthreads();
     if (t < NP) {
         double w[4];
         gradient_vars(qn, ph.gm1, w);
 #pragma unroll
         for (int c = 0; c < 4; ++c) sh[c * NP + t] = w[c];
     }
+    __syncthreads();
     // edge values: the common values of a tangential face pair (axis dp,
     // side sg), interpolated along the face normal to the face's edge
     for (int tau = t; tau < NET; tau += S::NT) {
@@ -746,7 +747,6 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) sh[v * NP + t] = D.q[v * vstride + node];
     }
-    __syncthreads();
 
 #pragma unroll
     for (int r = 0; r < S::TPT; ++r) {
@@ -755,7 +755,12 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
             const int f = tau / NF, fn = tau - f * NF;
             const int d = f >> 1;
             double qi[5], qo[5];
-            face_interp<PP, 5>(sh, B, f, fn, qi);
+            // the element's own trace on this face, written with the state
+            // by the trace epilogue (the same line interpolation of the
+            // same values, so the same numbers as interpolating sh here)
+            const double* ti = D.qtr_in + (size_t)(e * 6 + f) * 5 * NF + fn;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qi[v] = ti[v * NF];
             const int nb = neighbour_at(e, D.N, ecx, ecy, ecz, f);
             const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
 #pragma unroll
