@@ -36,10 +36,9 @@ struct Shape {
     // minimum wavefronts per SIMD that the stage kernels are compiled for:
     // five lets three blocks of 4 - 6 wavefronts share a CU (P = 4 - 6;
     // P = 3 is bound by LDS, P >= 7 by the registers it needs), where the
-    // kernel fits the registers that leaves without spilling (k_grad at
-    // P = 6 does not, and is slower at five)
+    // kernel fits the registers that leaves without spilling
     static constexpr int WPE = (PP >= 5 && PP <= 7) ? 5 : 2;
-    static constexpr int GRAD_WPE = (PP == 5 || PP == 6) ? 5 : 2;
+    static constexpr int GRAD_WPE = (PP >= 5 && PP <= 7) ? 5 : 2;
 };
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
@@ -728,8 +727,12 @@ __global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per
 k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     using S = Shape<PP>;
     constexpr int NP = S::NP, NF = S::NF;
-    __shared__ double sh[5 * NP + 54 * NF];
-    double* fhat = sh + 5 * NP;          // [6][5][NF] net interface flux
+    // P = 8 (one block per CU): the three directions' node fluxes are
+    // stored at once, so the flux divergence needs one barrier, not six
+    constexpr bool DIV3 = PP >= 9;
+    __shared__ double sh[(DIV3 ? 20 : 5) * NP + 54 * NF];
+    double* fhat = sh + (DIV3 ? 20 : 5) * NP;   // [6][5][NF] net interface flux
+    double* G3 = sh + 5 * NP;                     // DIV3: [3][5][NP] node fluxes
     double* what = fhat + 30 * NF;       // [6][4][NF] common BR1 values
     const int b = blockIdx.x;
     const int si = find_solve(dl, b);
@@ -743,9 +746,19 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     const size_t node = (size_t)e * NP + t;
     const size_t vstride = (size_t)E * NP;
 
-    if (t < NP) {
+    // The face phase works on traces only, so the node's own state goes
+    // straight to registers: loaded with the face data, and the Runge-Kutta
+    // register with it, where registers are to spare (P = 8, one block per
+    // CU), otherwise after the face phase.
+    constexpr bool QEARLY = PP >= 9;
+    double qn[5], kp[5];
+    if (QEARLY && t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sh[v * NP + t] = D.q[v * vstride + node];
+        for (int v = 0; v < 5; ++v) qn[v] = D.q[v * vstride + node];
+        if (UPDATE && !first_stage) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) kp[v] = D.k[v * vstride + node];
+        }
     }
 
 #pragma unroll
@@ -792,12 +805,9 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     }
     __syncthreads();
 
-    // the node's own state, read back after the face phase so that it holds
-    // no registers there
-    double qn[5];
-    if (t < NP) {
+    if (!QEARLY && t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qn[v] = sh[v * NP + t];
+        for (int v = 0; v < 5; ++v) qn[v] = D.q[v * vstride + node];
     }
     double g[3][4];
     if (ph.viscous) {
@@ -823,25 +833,53 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     NodeState ns;
     if (t < NP) node_state(qn, g, ph, ns);
     double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        __syncthreads();
+    if constexpr (DIV3) {
         if (t < NP) {
             double G[5];
-            if (d == 0) flux_net<0>(qn, ns, ph, G);
-            else if (d == 1) flux_net<1>(qn, ns, ph, G);
-            else flux_net<2>(qn, ns, ph, G);
+            flux_net<0>(qn, ns, ph, G);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) sh[v * NP + t] = G[v];
+            for (int v = 0; v < 5; ++v) G3[v * NP + t] = G[v];
+            flux_net<1>(qn, ns, ph, G);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) G3[(5 + v) * NP + t] = G[v];
+            flux_net<2>(qn, ns, ph, G);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) G3[(10 + v) * NP + t] = G[v];
         }
         __syncthreads();
         if (t < NP) {
             double dv[5];
-            if (d == 0) weak_deriv<PP, 0, 5>(sh, fhat, B, t, ph.s, dv);
-            else if (d == 1) weak_deriv<PP, 1, 5>(sh, fhat, B, t, ph.s, dv);
-            else weak_deriv<PP, 2, 5>(sh, fhat, B, t, ph.s, dv);
+            weak_deriv<PP, 0, 5>(G3, fhat, B, t, ph.s, dv);
 #pragma unroll
             for (int v = 0; v < 5; ++v) R[v] -= dv[v];
+            weak_deriv<PP, 1, 5>(G3 + 5 * NP, fhat, B, t, ph.s, dv);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) R[v] -= dv[v];
+            weak_deriv<PP, 2, 5>(G3 + 10 * NP, fhat, B, t, ph.s, dv);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) R[v] -= dv[v];
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            __syncthreads();
+            if (t < NP) {
+                double G[5];
+                if (d == 0) flux_net<0>(qn, ns, ph, G);
+                else if (d == 1) flux_net<1>(qn, ns, ph, G);
+                else flux_net<2>(qn, ns, ph, G);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sh[v * NP + t] = G[v];
+            }
+            __syncthreads();
+            if (t < NP) {
+                double dv[5];
+                if (d == 0) weak_deriv<PP, 0, 5>(sh, fhat, B, t, ph.s, dv);
+                else if (d == 1) weak_deriv<PP, 1, 5>(sh, fhat, B, t, ph.s, dv);
+                else weak_deriv<PP, 2, 5>(sh, fhat, B, t, ph.s, dv);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) R[v] -= dv[v];
+            }
         }
     }
 
@@ -861,14 +899,14 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     if (t < NP) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            const double kk = first_stage ? D.dt * R[v] : rkA * D.k[v * vstride + node] + D.dt * R[v];
+            const double kk = first_stage ? D.dt * R[v] : rkA * (QEARLY ? kp[v] : D.k[v * vstride + node]) + D.dt * R[v];
             qn[v] += rkB * kk;
             if (D.post) qn[v] += D.dt * D.post[v * vstride + node];
             D.k[v * vstride + node] = kk;
             D.q[v * vstride + node] = qn[v];
         }
     }
-    __syncthreads();
+    if (!DIV3) __syncthreads();
     if (t < NP) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) sh[v * NP + t] = qn[v];
