@@ -43,6 +43,14 @@ struct Shape {
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// Global-memory views of the arrays a solve descriptor points to.  Pointers
+// read from a descriptor in memory are generic, and generic (flat) accesses
+// count against the LDS counter as well: every LDS access would then wait
+// for the element's global loads and stores in flight.
+using gdouble = __attribute__((address_space(1))) double;
+__device__ __forceinline__ gdouble* gmem(double* p) { return (gdouble*)p; }
+__device__ __forceinline__ const gdouble* gmem(const double* p) { return (const gdouble*)p; }
+
 __device__ __forceinline__ int find_solve(const DescList& dl, int b) {
     int s = 0;
     for (int i = 1; i < dl.n; ++i)
@@ -415,7 +423,7 @@ __device__ __forceinline__ void line_interp(const double* __restrict__ sh, const
 // the six face traces of the nodal state in LDS, to global
 template <int PP>
 __device__ __forceinline__ void write_traces(const double* __restrict__ sh, const BasisTab& B, int t, int e,
-                                             double* __restrict__ out) {
+                                             gdouble* __restrict__ out) {
     using S = Shape<PP>;
     using Ln = Lines<PP>;
 #pragma unroll
@@ -425,8 +433,8 @@ __device__ __forceinline__ void write_traces(const double* __restrict__ sh, cons
             const int d = tau / S::NF, fn = tau - d * S::NF;
             double qm[5], qp[5];
             line_interp<PP, 5>(sh, B, d, fn, qm, qp);
-            double* om = out + (size_t)(e * 6 + 2 * d) * 5 * S::NF + fn;
-            double* op = om + 5 * S::NF;
+            gdouble* om = out + (size_t)(e * 6 + 2 * d) * 5 * S::NF + fn;
+            gdouble* op = om + 5 * S::NF;
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 om[v * S::NF] = qm[v];
@@ -450,9 +458,9 @@ __global__ void __launch_bounds__(Shape<PP>::NT) k_traces(DescList dl) {
     const int t = threadIdx.x;
     const BasisTab& B = c_basis[PP - 2];
     if (t < S::NP)
-        for (int v = 0; v < 5; ++v) sh[v * S::NP + t] = D.q[((size_t)v * E + e) * S::NP + t];
+        for (int v = 0; v < 5; ++v) sh[v * S::NP + t] = gmem(D.q)[((size_t)v * E + e) * S::NP + t];
     __syncthreads();
-    write_traces<PP>(sh, B, t, e, D.qtr_out);
+    write_traces<PP>(sh, B, t, e, gmem(D.qtr_out));
 }
 
 // BR1 pass, volume form: the lifted gradient at every node, then its face
@@ -477,7 +485,7 @@ __device__ __forceinline__ void grad_volume_form(const DescList& dl) {
     double qn[5];
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qn[v] = D.q[((size_t)v * E + e) * NP + t];
+        for (int v = 0; v < 5; ++v) qn[v] = gmem(D.q)[((size_t)v * E + e) * NP + t];
     }
 
     double fq[S::TPT][4];   // own traced (rho, u, v, w) per face task
@@ -490,11 +498,11 @@ __device__ __forceinline__ void grad_volume_form(const DescList& dl) {
             // the element's own trace on this face, written with the state
             // by the trace epilogue (the same line interpolation of the
             // same values, so the same numbers as interpolating sh here)
-            const double* ti = D.qtr_in + (size_t)(e * 6 + f) * 5 * NF + fn;
+            const gdouble* ti = gmem(D.qtr_in) + (size_t)(e * 6 + f) * 5 * NF + fn;
 #pragma unroll
             for (int v = 0; v < 5; ++v) qi[v] = ti[v * NF];
             const int nb = neighbour_at(e, D.N, ecx, ecy, ecz, f);
-            const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
+            const gdouble* tr = gmem(D.qtr_in) + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
 #pragma unroll
             for (int v = 0; v < 5; ++v) qo[v] = tr[v * NF];
             double wi[4], wo[4];
@@ -544,7 +552,7 @@ __device__ __forceinline__ void grad_volume_form(const DescList& dl) {
             const double v[3] = {fq[r][1], fq[r][2], fq[r][3]};
             double Fv[4];
             flux_viscous_rot(f >> 1, fq[r][0], v, gf, ph, Fv);
-            double* o = D.fv + (size_t)(e * 6 + f) * 4 * NF + fn;
+            gdouble* o = gmem(D.fv) + (size_t)(e * 6 + f) * 4 * NF + fn;
 #pragma unroll
             for (int c = 0; c < 4; ++c) o[c * NF] = Fv[c];
         }
@@ -580,7 +588,7 @@ __device__ __forceinline__ void grad_face_form(const DescList& dl) {
     double qn[5];
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qn[v] = D.q[((size_t)v * E + e) * NP + t];
+        for (int v = 0; v < 5; ++v) qn[v] = gmem(D.q)[((size_t)v * E + e) * NP + t];
     }
 
     double fq[S::TPT][4];   // own traced (rho, u, v, w) per face task
@@ -593,11 +601,11 @@ __device__ __forceinline__ void grad_face_form(const DescList& dl) {
             // the element's own trace on this face, written with the state
             // by the trace epilogue (the same line interpolation of the
             // same values, so the same numbers as interpolating sh here)
-            const double* ti = D.qtr_in + (size_t)(e * 6 + f) * 5 * NF + fn;
+            const gdouble* ti = gmem(D.qtr_in) + (size_t)(e * 6 + f) * 5 * NF + fn;
 #pragma unroll
             for (int v = 0; v < 5; ++v) qi[v] = ti[v * NF];
             const int nb = neighbour_at(e, D.N, ecx, ecy, ecz, f);
-            const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
+            const gdouble* tr = gmem(D.qtr_in) + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
 #pragma unroll
             for (int v = 0; v < 5; ++v) qo[v] = tr[v * NF];
             double wi[4], wo[4];
@@ -703,7 +711,7 @@ __device__ __forceinline__ void grad_face_form(const DescList& dl) {
             const double v[3] = {fq[r][1], fq[r][2], fq[r][3]};
             double Fv[4];
             flux_viscous_rot(d, fq[r][0], v, gf, ph, Fv);
-            double* o = D.fv + (size_t)(e * 6 + f) * 4 * NF + fn;
+            gdouble* o = gmem(D.fv) + (size_t)(e * 6 + f) * 4 * NF + fn;
 #pragma unroll
             for (int c = 0; c < 4; ++c) o[c * NF] = Fv[c];
         }
@@ -754,10 +762,10 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     double qn[5], kp[5];
     if (QEARLY && t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qn[v] = D.q[v * vstride + node];
+        for (int v = 0; v < 5; ++v) qn[v] = gmem(D.q)[v * vstride + node];
         if (UPDATE && !first_stage) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) kp[v] = D.k[v * vstride + node];
+            for (int v = 0; v < 5; ++v) kp[v] = gmem(D.k)[v * vstride + node];
         }
     }
 
@@ -771,11 +779,11 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
             // the element's own trace on this face, written with the state
             // by the trace epilogue (the same line interpolation of the
             // same values, so the same numbers as interpolating sh here)
-            const double* ti = D.qtr_in + (size_t)(e * 6 + f) * 5 * NF + fn;
+            const gdouble* ti = gmem(D.qtr_in) + (size_t)(e * 6 + f) * 5 * NF + fn;
 #pragma unroll
             for (int v = 0; v < 5; ++v) qi[v] = ti[v * NF];
             const int nb = neighbour_at(e, D.N, ecx, ecy, ecz, f);
-            const double* tr = D.qtr_in + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
+            const gdouble* tr = gmem(D.qtr_in) + (size_t)(nb * 6 + (f ^ 1)) * 5 * NF + fn;
 #pragma unroll
             for (int v = 0; v < 5; ++v) qo[v] = tr[v * NF];
             // the lower-side state is the neighbour's on a lower face
@@ -789,8 +797,8 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
             double F[5];
             flux_roe_rot(d, qL, qR, ph, F);
             if (ph.viscous) {
-                const double* fi = D.fv + (size_t)(e * 6 + f) * 4 * NF + fn;
-                const double* fo = D.fv + (size_t)(nb * 6 + (f ^ 1)) * 4 * NF + fn;
+                const gdouble* fi = gmem(D.fv) + (size_t)(e * 6 + f) * 4 * NF + fn;
+                const gdouble* fo = gmem(D.fv) + (size_t)(nb * 6 + (f ^ 1)) * 4 * NF + fn;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) F[1 + c] -= 0.5 * (fi[c * NF] + fo[c * NF]);
                 double wi[4], wo[4];
@@ -807,7 +815,7 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
 
     if (!QEARLY && t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qn[v] = D.q[v * vstride + node];
+        for (int v = 0; v < 5; ++v) qn[v] = gmem(D.q)[v * vstride + node];
     }
     double g[3][4];
     if (ph.viscous) {
@@ -885,13 +893,13 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
 
     if (t < NP && D.forcing) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) R[v] += D.forcing[v * vstride + node];
+        for (int v = 0; v < 5; ++v) R[v] += gmem(D.forcing)[v * vstride + node];
     }
 
     if (!UPDATE) {
         if (t < NP) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) D.out[v * vstride + node] = R[v];
+            for (int v = 0; v < 5; ++v) gmem(D.out)[v * vstride + node] = R[v];
         }
         return;
     }
@@ -899,11 +907,11 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     if (t < NP) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            const double kk = first_stage ? D.dt * R[v] : rkA * (QEARLY ? kp[v] : D.k[v * vstride + node]) + D.dt * R[v];
+            const double kk = first_stage ? D.dt * R[v] : rkA * (QEARLY ? kp[v] : gmem(D.k)[v * vstride + node]) + D.dt * R[v];
             qn[v] += rkB * kk;
-            if (D.post) qn[v] += D.dt * D.post[v * vstride + node];
-            D.k[v * vstride + node] = kk;
-            D.q[v * vstride + node] = qn[v];
+            if (D.post) qn[v] += D.dt * gmem(D.post)[v * vstride + node];
+            gmem(D.k)[v * vstride + node] = kk;
+            gmem(D.q)[v * vstride + node] = qn[v];
         }
     }
     if (!DIV3) __syncthreads();
@@ -912,7 +920,7 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
         for (int v = 0; v < 5; ++v) sh[v * NP + t] = qn[v];
     }
     __syncthreads();
-    write_traces<PP>(sh, B, t, e, D.qtr_out);
+    write_traces<PP>(sh, B, t, e, gmem(D.qtr_out));
 }
 
 // Taylor-Green vortex initial condition, Eq. (11), on [0, L]^3.

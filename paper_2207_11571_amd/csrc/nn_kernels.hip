@@ -21,6 +21,15 @@ namespace dgnn {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Global-memory views of pointers taken from the argument structs: indexed
+// by a run-time layer number they reach the kernel as generic pointers, and
+// generic (flat) accesses count against the LDS counter as well, so LDS
+// accesses would wait for the global traffic in flight.
+template <class T>
+using global_t = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ global_t<T>* gmem(T* p) { return (global_t<T>*)p; }
+
 constexpr int kRows = 16;      // rows (elements / samples) per block
 constexpr int kThreads = 256;     // weight-gradient blocks: four wavefronts, one tile each
 constexpr int kRowWaves = 16;     // row-block kernels: sixteen wavefronts share the column tiles
@@ -50,16 +59,17 @@ __device__ __forceinline__ float act_bwd(float h, int act) { return act == 0 ? 1
 // wavefronts (one or two tiles each) beat fewer wavefronts with prefetching.
 template <int KP, class Epi>
 __device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, int ldA,
-                                               const uint16_t* __restrict__ W, int Np, int wave, int lane, Epi& epi) {
+                                               const global_t<uint16_t>* __restrict__ W, int Np, int wave, int lane,
+                                               Epi& epi) {
     constexpr int KS = KP / 32;
     const int kq = 8 * (lane >> 4);
     const int r = lane & 15;
     const uint16_t* arow = sA + r * ldA + kq;
     for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
-        const uint16_t* wrow = W + (size_t)(tile * 16 + r) * KP + kq;
+        const global_t<uint16_t>* wrow = W + (size_t)(tile * 16 + r) * KP + kq;
         bf16x8 b[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) b[s] = *(const bf16x8*)(wrow + 32 * s);
+        for (int s = 0; s < KS; ++s) b[s] = *(const global_t<bf16x8>*)(wrow + 32 * s);
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
@@ -73,8 +83,9 @@ __device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, 
 }
 
 template <class Epi>
-__device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ldA, const uint16_t* __restrict__ W,
-                                         int Kp, int Np, int wave, int lane, Epi epi) {
+__device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ldA,
+                                         const global_t<uint16_t>* __restrict__ W, int Kp, int Np, int wave, int lane,
+                                         Epi epi) {
     if (Kp == 256) {
         tile_mma_fixed<256>(sA, ldA, W, Np, wave, lane, epi);
         return;
@@ -88,11 +99,11 @@ __device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ld
     for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         const int n = tile * 16 + r;
-        const uint16_t* wrow = W + (size_t)n * Kp + kq;
+        const global_t<uint16_t>* wrow = W + (size_t)n * Kp + kq;
         const uint16_t* arow = sA + r * ldA + kq;
         for (int k0 = 0; k0 < Kp; k0 += 32) {
             const bf16x8 a = *(const bf16x8*)(arow + k0);
-            const bf16x8 b = *(const bf16x8*)(wrow + k0);
+            const bf16x8 b = *(const global_t<bf16x8>*)(wrow + k0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
@@ -161,15 +172,15 @@ __global__ void __launch_bounds__(kRowThreads) k_net_forcing(NetArgs na, int NP,
     const int L = na.n_layers;
     for (int l = 0; l < L; ++l) {
         const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
-        const float* bias = na.b[l];
+        const global_t<const float>* bias = gmem(na.b[l]);
         if (l < L - 1) {
             const int act = na.act;
-            tile_mma(bufA, ld, na.W[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+            tile_mma(bufA, ld, gmem(na.W[l]), Kp, Np, wave, lane, [&](int m, int n, float v) {
                 const float z = v + (n < Nd ? bias[n] : 0.0f);
                 bufB[m * ld + n] = f2bf(n < Nd ? act_fwd(z, act) : 0.0f);
             });
         } else {
-            tile_mma(bufA, ld, na.W[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+            tile_mma(bufA, ld, gmem(na.W[l]), Kp, Np, wave, lane, [&](int m, int n, float v) {
                 const int e = e0 + m;
                 if (e < E && n < Nd) {
                     const float y = v + bias[n];
@@ -223,9 +234,8 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
     int pmax = 0;
     for (int l = 0; l <= L; ++l) pmax = pmax > na.pdims[l] ? pmax : na.pdims[l];
     const int ld = pmax + kLdPad;
-    // act[0..L-1] then two gradient buffers
-    uint16_t* act[kMaxLayers];
-    for (int l = 0; l < L; ++l) act[l] = smem + l * kRows * ld;
+    // act(0..L-1) then two gradient buffers
+    auto act = [&](int l) { return smem + l * kRows * ld; };
     uint16_t* g0 = smem + L * kRows * ld;
     uint16_t* g1 = g0 + kRows * ld;
     __shared__ float red[kRowThreads];
@@ -253,16 +263,16 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
                 x = (float)((xv - na.mu_in[v]) / na.sig_in[v]);
             }
         }
-        act[0][r * ld + c] = f2bf(x);
+        act(0)[r * ld + c] = f2bf(x);
     }
     __syncthreads();
     // forward through the hidden layers
     for (int l = 0; l < L - 1; ++l) {
         const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
-        const float* bias = na.b[l];
-        uint16_t* out = act[l + 1];
+        const global_t<const float>* bias = gmem(na.b[l]);
+        uint16_t* out = act(l + 1);
         const int a = na.act;
-        tile_mma(act[l], ld, na.W[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+        tile_mma(act(l), ld, gmem(na.W[l]), Kp, Np, wave, lane, [&](int m, int n, float v) {
             const float z = v + (n < Nd ? bias[n] : 0.0f);
             out[m * ld + n] = f2bf(n < Nd ? act_fwd(z, a) : 0.0f);
         });
@@ -275,8 +285,8 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
         const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
         const int npv_out = Nd / na.n_out;
         const size_t yw = (size_t)5 * npv_out;
-        const float* bias = na.b[l];
-        tile_mma(act[l], ld, na.W[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+        const global_t<const float>* bias = gmem(na.b[l]);
+        tile_mma(act(l), ld, gmem(na.W[l]), Kp, Np, wave, lane, [&](int m, int n, float v) {
             const int row = r0 + m;
             float dy = 0.0f;
             if (row < B && n < Nd) {
@@ -305,21 +315,21 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
     for (int c = t; c < na.pdims[L]; c += kRowThreads) {
         float sacc = 0.0f;
         for (int rr = 0; rr < kRows; ++rr) sacc += bf2f(g0[rr * ld + c]);
-        ta.bias_part[L - 1][(size_t)blockIdx.x * na.pdims[L] + c] = sacc;
+        gmem(ta.bias_part[L - 1])[(size_t)blockIdx.x * na.pdims[L] + c] = sacc;
     }
     // transposed activations and dz_{L-1}
     for (int l = 0; l < L; ++l) {
         const int pd = na.pdims[l];
         for (int idx = t; idx < pd * kRows; idx += kRowThreads) {
             const int c = idx / kRows, r = idx - c * kRows;
-            ta.actT[l][(size_t)c * Bp + r0 + r] = act[l][r * ld + c];
+            gmem(ta.actT[l])[(size_t)c * Bp + r0 + r] = act(l)[r * ld + c];
         }
     }
     {
         const int pd = na.pdims[L];
         for (int idx = t; idx < pd * kRows; idx += kRowThreads) {
             const int c = idx / kRows, r = idx - c * kRows;
-            ta.dzT[L - 1][(size_t)c * Bp + r0 + r] = g0[r * ld + c];
+            gmem(ta.dzT[L - 1])[(size_t)c * Bp + r0 + r] = g0[r * ld + c];
         }
     }
     // backward data chain
@@ -327,21 +337,21 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
     uint16_t* gout = g1;
     for (int l = L - 1; l >= 1; --l) {
         const int Kp = na.pdims[l + 1], Np = na.pdims[l], Nd = na.dims[l];
-        const uint16_t* h = act[l];
+        const uint16_t* h = act(l);
         const int a = na.act;
-        tile_mma(gin, ld, na.WT[l], Kp, Np, wave, lane, [&](int m, int n, float v) {
+        tile_mma(gin, ld, gmem(na.WT[l]), Kp, Np, wave, lane, [&](int m, int n, float v) {
             const float d = (n < Nd) ? v * act_bwd(bf2f(h[m * ld + n]), a) : 0.0f;
             gout[m * ld + n] = f2bf(r0 + m < B ? d : 0.0f);
         });
         __syncthreads();
         for (int idx = t; idx < Np * kRows; idx += kRowThreads) {
             const int c = idx / kRows, r = idx - c * kRows;
-            ta.dzT[l - 1][(size_t)c * Bp + r0 + r] = gout[r * ld + c];
+            gmem(ta.dzT[l - 1])[(size_t)c * Bp + r0 + r] = gout[r * ld + c];
         }
         for (int c = t; c < Np; c += kRowThreads) {
             float sacc = 0.0f;
             for (int rr = 0; rr < kRows; ++rr) sacc += bf2f(gout[rr * ld + c]);
-            ta.bias_part[l - 1][(size_t)blockIdx.x * Np + c] = sacc;
+            gmem(ta.bias_part[l - 1])[(size_t)blockIdx.x * Np + c] = sacc;
         }
         uint16_t* tmp = gin;
         gin = gout;

@@ -72,7 +72,9 @@ def test_residual_tgv_C1(B):
 
 @pytest.mark.parametrize("N,P,Cs,viscous", [
     (3, 1, 0.0, True), (3, 2, 0.1, True), (3, 3, 0.0, False), (2, 4, 0.1, True),
-    (3, 5, 0.0, True), (2, 6, 0.1, True), (2, 7, 0.0, True), (2, 8, 0.1, True), (1, 3, 0.0, True)])
+    (3, 5, 0.0, True), (2, 6, 0.1, True), (2, 7, 0.0, True), (2, 8, 0.1, True), (1, 3, 0.0, True),
+    # 343 elements at P = 8: more blocks than the GPU holds at once
+    (7, 8, 0.1, True), (7, 8, 0.0, False)])
 def test_residual_random_states(B, N, P, Cs, viscous):
     say("residual random", N, P, Cs, viscous)
     q = synthetic.random_state(N, P, seed=100 + 10 * N + P)
@@ -163,7 +165,7 @@ def test_rk_steps_C1(B):
     assert np.all(l2 < 1e-12) and np.all(li < 1e-11), (l2, li)
 
 
-@pytest.mark.parametrize("N,P,Cs", [(3, 4, 0.1), (2, 6, 0.0)])
+@pytest.mark.parametrize("N,P,Cs", [(3, 4, 0.1), (2, 6, 0.0), (7, 8, 0.1)])
 def test_rk_steps_random(B, N, P, Cs):
     dg, forcing, projection, rk = _oracle()
     say("rk random", N, P, Cs)

@@ -55,6 +55,9 @@ MIX = [
     dict(Re=200.0, P=3, N=8, use_nn=True),
     dict(Re=30.0, P=6, N=2),
     dict(Re=200.0, P=3, N=4, use_nn=True, after_step=True),
+    # with the P = 8 solve above, 407 elements of two solves in one P = 8
+    # launch
+    dict(Re=1600.0, P=8, N=7),
 ]
 
 
