@@ -137,7 +137,10 @@ int dg_rk_step_noalloc(const dg_mesh* m, double* q, double* k, double dt, int32_
  * event pair on `stream`; out_ms (host, double[4]) receives the mean duration
  * in milliseconds of one launch of each stage kernel: [0] face traces,
  * [1] BR1 gradient pass, [2] network forcing (0 without a model),
- * [3] residual + stage update.  Synchronises `stream`. */
+ * [3] residual + stage update.  Where the BR1 pass and the network run as
+ * one launch (P = 3 with a model reading all nodes of its variables, viscous,
+ * E a multiple of 16) that launch is reported in [2] and [1] is 0.
+ * Synchronises `stream`. */
 int dg_profile_steps(const dg_mesh* m, double* q, double* k, double dt, int32_t n_steps,
                      const nn_model* forcing, void* ws, size_t ws_bytes, void* stream, double* out_ms);
 

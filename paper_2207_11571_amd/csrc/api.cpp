@@ -273,6 +273,8 @@ int rk_impl(const Mesh& m, double* q, double* k, double dt, int n_steps, const n
     DescList dl[4];
     for (int p = 0; p < 4; ++p) dl[p] = single_list(dd + p, m.E);
     DG_HIP(launch_traces(m.PP, dl[1], st));   // traces of q into qtr0
+    // forcing at every stage at P = 3: BR1 pass and network in one launch
+    const bool fused = model && !post && grad_net_fusable(model, m);
     int par = 0;
     for (int n = 0; n < n_steps; ++n) {
         // post-step correction (Algorithm 1): s from the state at the start of the step
@@ -282,10 +284,15 @@ int rk_impl(const Mesh& m, double* q, double* k, double dt, int n_steps, const n
         }
         for (int s = 0; s < 3; ++s) {
             const DescList& l = dl[(post && model && s == 2 ? 2 : 0) + par];
-            if (m.ph.viscous) DG_HIP(launch_grad(m.PP, l, st));
-            if (model && !post) {
-                int rc = net_forcing_impl(model, m, q, (double*)(ws + L.forcing), /*accumulate=*/0, st);
+            if (fused) {
+                int rc = grad_net_impl(model, m, l, q, (double*)(ws + L.forcing), st);
                 if (rc != DG_OK) return rc;
+            } else {
+                if (m.ph.viscous) DG_HIP(launch_grad(m.PP, l, st));
+                if (model && !post) {
+                    int rc = net_forcing_impl(model, m, q, (double*)(ws + L.forcing), /*accumulate=*/0, st);
+                    if (rc != DG_OK) return rc;
+                }
             }
             DG_HIP(launch_resid(m.PP, 1, l, kRkA[s], kRkB[s], s == 0, st));
             par ^= 1;
@@ -484,15 +491,22 @@ int dg_profile_steps(const dg_mesh* mh, double* q, double* k, double dt, int32_t
             err = set_error(DG_EHIP, "trace launch failed");
             break;
         }
+        const bool fused = model && grad_net_fusable(model, m);
         int par = 0;
         for (int n = 0; n < n_steps && err == DG_OK; ++n)
             for (int s = 0; s < 3 && err == DG_OK; ++s) {
-                if (m.ph.viscous) {
+                if (fused) {
+                    // the fused BR1-and-network launch, timed as the network's
+                    if (mark(2) != hipSuccess) err = set_error(DG_EHIP, "event failed");
+                    else if ((err = grad_net_impl(model, m, dl[par], q, (double*)(ws + L.forcing), st)) == DG_OK &&
+                             hipEventRecord(ev[ie++], st) != hipSuccess)
+                        err = set_error(DG_EHIP, "event failed");
+                } else if (m.ph.viscous) {
                     if (mark(1) != hipSuccess || launch_grad(m.PP, dl[par], st) != hipSuccess ||
                         hipEventRecord(ev[ie++], st) != hipSuccess)
                         err = set_error(DG_EHIP, "grad launch failed");
                 }
-                if (model && err == DG_OK) {
+                if (model && !fused && err == DG_OK) {
                     if (mark(2) != hipSuccess) err = set_error(DG_EHIP, "event failed");
                     else if ((err = net_forcing_impl(model, m, q, (double*)(ws + L.forcing), 0, st)) == DG_OK &&
                              hipEventRecord(ev[ie++], st) != hipSuccess)

@@ -21,6 +21,7 @@
 #include <mutex>
 
 #include "dgnn_internal.hpp"
+#include "nn_device.hpp"
 
 namespace dgnn {
 
@@ -43,13 +44,12 @@ struct Shape {
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-// Global-memory views of the arrays a solve descriptor points to.  Pointers
-// read from a descriptor in memory are generic, and generic (flat) accesses
-// count against the LDS counter as well: every LDS access would then wait
-// for the element's global loads and stores in flight.
-using gdouble = __attribute__((address_space(1))) double;
-__device__ __forceinline__ gdouble* gmem(double* p) { return (gdouble*)p; }
-__device__ __forceinline__ const gdouble* gmem(const double* p) { return (const gdouble*)p; }
+// The arrays a solve descriptor points to are addressed through gmem()
+// (global memory): read from a descriptor in memory they are generic
+// pointers, and generic (flat) accesses count against the LDS counter as
+// well, so every LDS access would wait for the element's global loads and
+// stores in flight.
+using gdouble = global_t<double>;
 
 __device__ __forceinline__ int find_solve(const DescList& dl, int b) {
     int s = 0;
@@ -466,23 +466,23 @@ __global__ void __launch_bounds__(Shape<PP>::NT) k_traces(DescList dl) {
 // BR1 pass, volume form: the lifted gradient at every node, then its face
 // interpolation.
 template <int PP>
-__device__ __forceinline__ void grad_volume_form(const DescList& dl) {
+struct GradLds {
+    static constexpr int N = cmax(12 * Shape<PP>::NP, 5 * Shape<PP>::NP + 24 * Shape<PP>::NF);
+};
+
+// element e of solve D, thread t of the element's Shape<PP>::NT, LDS area sh
+// of GradLds<PP>::N doubles; the node's state is left in qn (t < NP)
+template <int PP>
+__device__ __forceinline__ void grad_volume_element(const SolveDesc& D, int e, int t, double* __restrict__ sh,
+                                                    double qn[5]) {
     using S = Shape<PP>;
     constexpr int NP = S::NP, NF = S::NF;
-    constexpr int LDS = cmax(12 * NP, 5 * NP + 24 * NF);
-    __shared__ double sh[LDS];
     double* what = sh + 5 * NP;                  // [6][4][NF] common BR1 values
-    const int b = blockIdx.x;
-    const int si = find_solve(dl, b);
-    const SolveDesc& D = *dl.d[si];
     const Phys ph = D.ph;
-    const int e = b - dl.blk[si];
     const int ecx = e % D.N, ecy = (e / D.N) % D.N, ecz = e / (D.N * D.N);
     const int E = D.E;
-    const int t = threadIdx.x;
     const BasisTab& B = c_basis[PP - 2];
 
-    double qn[5];
     if (t < NP) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) qn[v] = gmem(D.q)[((size_t)v * E + e) * NP + t];
@@ -557,6 +557,15 @@ __device__ __forceinline__ void grad_volume_form(const DescList& dl) {
             for (int c = 0; c < 4; ++c) o[c * NF] = Fv[c];
         }
     }
+}
+
+template <int PP>
+__device__ __forceinline__ void grad_volume_form(const DescList& dl) {
+    __shared__ double sh[GradLds<PP>::N];
+    const int b = blockIdx.x;
+    const int si = find_solve(dl, b);
+    double qn[5];
+    grad_volume_element<PP>(*dl.d[si], b - dl.blk[si], threadIdx.x, sh, qn);
 }
 
 // BR1 pass, face form: only the face values of the lifted gradient are needed here, so they are
@@ -726,6 +735,47 @@ __global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per
 k_grad(DescList dl) {
     if constexpr (PP >= 9) grad_face_form<PP>(dl);
     else grad_volume_form<PP>(dl);
+}
+
+// P = 3 with the forcing network at every stage (Eq. (4)): the BR1 pass of
+// sixteen elements, one per wavefront, and the network on the same sixteen
+// rows in one launch.  After the BR1 pass each wavefront holds its
+// element's state in registers (node n in lane n), so it writes the
+// element's normalised network input row straight into LDS instead of the
+// network gathering the state from HBM again, and the layers follow in the
+// same block.  The same device code as k_grad and k_net_forcing, so the same
+// numbers.  One solve per launch, E a multiple of 16.
+template <int PP>
+__global__ void __launch_bounds__(kRowThreads) k_grad_net(DescList dl, NetArgs na, NetTarget T) {
+    using S = Shape<PP>;
+    static_assert(S::NT == 64 && S::NP == 64, "one element per wavefront, one node per lane");
+    constexpr int NP = S::NP;
+    extern __shared__ __attribute__((aligned(16))) double gsm[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int pmax = 0;
+    for (int l = 0; l <= na.n_layers; ++l) pmax = pmax > na.pdims[l] ? pmax : na.pdims[l];
+    const int ld = pmax + kLdPad;
+    uint16_t* bufA = (uint16_t*)(gsm + kRowWaves * GradLds<PP>::N);
+    uint16_t* bufB = bufA + kRows * ld;
+    const SolveDesc& D = *dl.d[0];
+    const int e0 = blockIdx.x * kRows;
+
+    double qn[5];
+    grad_volume_element<PP>(D, e0 + wave, lane, gsm + wave * GradLds<PP>::N, qn);
+
+    // row `wave` of the network input: column j NP + n is node n of
+    // variable in_var[j]
+    const int din = na.dims[0], pin = na.pdims[0];
+    uint16_t* row = bufA + wave * ld;
+    for (int j = 0; j < na.n_in; ++j) {
+        const int v = na.in_var[j];
+        const double qv = v == 0 ? qn[0] : (v == 1 ? qn[1] : (v == 2 ? qn[2] : (v == 3 ? qn[3] : qn[4])));
+        row[j * NP + lane] = f2bf(net_input(na, NP, v, lane, qv));
+    }
+    for (int c = din + lane; c < pin; c += 64) row[c] = f2bf(0.0f);
+    net_zero_unforced(na, NP, T, e0, threadIdx.x);
+    __syncthreads();
+    net_block_forward(na, NP, T, e0, 0, bufA, bufB, ld, wave, lane);
 }
 
 // Residual (update == 0: out = p(q) + forcing) or Runge-Kutta stage
@@ -1202,6 +1252,19 @@ hipError_t launch_traces(int PPv, const DescList& dl, hipStream_t st) {
 hipError_t launch_grad(int PPv, const DescList& dl, hipStream_t st) {
     const int nb = dl.blk[dl.n];
     DG_DISPATCH_PP(PPv, hipLaunchKernelGGL(k_grad<PP>, dim3(nb), dim3(Shape<PP>::NT), 0, st, dl));
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_net(int PPv, const DescList& dl, const NetArgs& na, const NetTarget& T, hipStream_t st) {
+    if (PPv != 4 || dl.n != 1 || T.E % kRows != 0 || na.dims[0] != na.n_in * 64) return hipErrorInvalidValue;
+    int pmax = 0;
+    for (int l = 0; l <= na.n_layers; ++l) pmax = pmax > na.pdims[l] ? pmax : na.pdims[l];
+    const size_t smem = (size_t)kRowWaves * GradLds<4>::N * sizeof(double) +
+                        (size_t)2 * kRows * (pmax + kLdPad) * sizeof(uint16_t);
+    hipError_t e = hipFuncSetAttribute((const void*)k_grad_net<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_net<4>, dim3(T.E / kRows), dim3(kRowThreads), smem, st, dl, na, T);
     return hipGetLastError();
 }
 

@@ -137,6 +137,10 @@ void* scratch_device_ptr(int dev);
 hipError_t launch_write_descs(const SolveDesc* host, int n, SolveDesc* dev, hipStream_t st);
 hipError_t launch_traces(int PP, const DescList& dl, hipStream_t st);
 hipError_t launch_grad(int PP, const DescList& dl, hipStream_t st);
+// k_grad and the forcing network in one launch (P = 3, one solve, E a
+// multiple of 16, the network reading all n_p nodes of its variables);
+// hipErrorInvalidValue otherwise
+hipError_t launch_grad_net(int PP, const DescList& dl, const NetArgs& na, const NetTarget& T, hipStream_t st);
 hipError_t launch_resid(int PP, int update, const DescList& dl, double rkA, double rkB, int first_stage,
                         hipStream_t st);
 hipError_t launch_tgv(int PP, const Phys& ph, int N, double* q, hipStream_t st);

@@ -99,6 +99,23 @@ int net_forcing_impl(const nn_model* m, const Mesh& mesh, const double* q, doubl
     return DG_OK;
 }
 
+bool grad_net_fusable(const nn_model* m, const Mesh& mesh) {
+    return m && mesh.PP == 4 && mesh.ph.viscous && mesh.E % net_rows_per_block() == 0 &&
+           m->dims[0] == m->n_in * mesh.n_p;
+}
+
+int grad_net_impl(const nn_model* m, const Mesh& mesh, const DescList& dl, const double* q, double* out,
+                  hipStream_t st) {
+    const NetArgs na = net_args(m);
+    NetTarget tg;
+    tg.q = q;
+    tg.out = out;
+    tg.E = mesh.E;
+    tg.blk_begin = 0;
+    NN_HIP(launch_grad_net(mesh.PP, dl, na, tg, st));
+    return DG_OK;
+}
+
 int net_forcing_batch(const nn_model* m, int n_p, const NetTarget* targets, int nt, hipStream_t st) {
     const NetArgs na = net_args(m);
     const int rpb = net_rows_per_block();

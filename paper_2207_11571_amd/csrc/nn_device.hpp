@@ -1,0 +1,168 @@
+// Device code of the forcing network shared by the network kernels and the
+// fused BR1-and-network kernel of the stage: bf16 rounding, activations, the
+// 16-row MFMA layer product (v_mfma_f32_16x16x32_bf16, float32
+// accumulation) and the forward pass of one 16-row block whose normalised
+// inputs are in LDS.
+#pragma once
+
+#include "dgnn_internal.hpp"
+
+namespace dgnn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Global-memory views of pointers taken from the argument structs: indexed
+// by a run-time layer number they reach the kernel as generic pointers, and
+// generic (flat) accesses count against the LDS counter as well, so LDS
+// accesses would wait for the global traffic in flight.
+template <class T>
+using global_t = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ global_t<T>* gmem(T* p) { return (global_t<T>*)p; }
+
+constexpr int kRows = 16;      // rows (elements / samples) per block
+constexpr int kThreads = 256;     // weight-gradient blocks: four wavefronts, one tile each
+constexpr int kRowWaves = 16;     // row-block kernels: sixteen wavefronts share the column tiles
+constexpr int kRowThreads = 64 * kRowWaves;
+constexpr int kLdPad = 8;      // LDS row padding (bf16 elements)
+
+// float32 -> bfloat16, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x0040u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ __forceinline__ float act_fwd(float z, int act) { return act == 0 ? tanhf(z) : fmaxf(z, 0.0f); }
+// derivative through the output h = act(z)
+__device__ __forceinline__ float act_bwd(float h, int act) { return act == 0 ? 1.0f - h * h : (h > 0.0f ? 1.0f : 0.0f); }
+
+// C[16][Np] = A[16][Kp] W^T with W [Np][Kp] row-major bf16 in global memory.
+// Wave w computes the 16-column tiles w, w + kRowWaves, ...; epi(m, n, value)
+// per output.  For the common widths the K loop is unrolled so that all of a
+// tile's weight fragments are in flight at once: the weights come from L2 and
+// their latency, not the matrix cores, bounds this product, so sixteen
+// wavefronts (one or two tiles each) beat fewer wavefronts with prefetching.
+template <int KP, class Epi>
+__device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, int ldA,
+                                               const global_t<uint16_t>* __restrict__ W, int Np, int wave, int lane,
+                                               Epi& epi) {
+    constexpr int KS = KP / 32;
+    const int kq = 8 * (lane >> 4);
+    const int r = lane & 15;
+    const uint16_t* arow = sA + r * ldA + kq;
+    for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
+        const global_t<uint16_t>* wrow = W + (size_t)(tile * 16 + r) * KP + kq;
+        bf16x8 b[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) b[s] = *(const global_t<bf16x8>*)(wrow + 32 * s);
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const bf16x8 a = *(const bf16x8*)(arow + 32 * s);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], acc, 0, 0, 0);
+        }
+        const int n = tile * 16 + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) epi(4 * (lane >> 4) + i, n, acc[i]);
+    }
+}
+
+template <class Epi>
+__device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ldA,
+                                         const global_t<uint16_t>* __restrict__ W, int Kp, int Np, int wave, int lane,
+                                         Epi epi) {
+    if (Kp == 256) {
+        tile_mma_fixed<256>(sA, ldA, W, Np, wave, lane, epi);
+        return;
+    }
+    if (Kp == 320) {
+        tile_mma_fixed<320>(sA, ldA, W, Np, wave, lane, epi);
+        return;
+    }
+    const int kq = 8 * (lane >> 4);
+    const int r = lane & 15;
+    for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int n = tile * 16 + r;
+        const global_t<uint16_t>* wrow = W + (size_t)n * Kp + kq;
+        const uint16_t* arow = sA + r * ldA + kq;
+        for (int k0 = 0; k0 < Kp; k0 += 32) {
+            const bf16x8 a = *(const bf16x8*)(arow + k0);
+            const bf16x8 b = *(const global_t<bf16x8>*)(wrow + k0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) epi(4 * (lane >> 4) + i, n, acc[i]);
+    }
+}
+
+// normalised network input of node n of variable v, value qv (Sec. 2.2:
+// per-variable, or per-node when the model carries column statistics)
+__device__ __forceinline__ float net_input(const NetArgs& na, int NP, int v, int n, double qv) {
+    if (na.col) {
+        const int cc = v * NP + n;
+        return (float)((qv - na.col[cc]) / na.col[5 * NP + cc]);
+    }
+    return (float)((qv - na.mu_in[v]) / na.sig_in[v]);
+}
+
+// write mode: the variables the network does not force get s = 0 (rows
+// e0 .. e0 + 15 of target T)
+__device__ __forceinline__ void net_zero_unforced(const NetArgs& na, int NP, const NetTarget& T, int e0, int t) {
+    if (na.n_out >= 5) return;
+    const size_t vs = (size_t)T.E * NP;
+    for (int idx = t; idx < kRows * 5 * NP; idx += kRowThreads) {
+        const int r = idx / (5 * NP), c = idx - r * (5 * NP);
+        const int v = c / NP, n = c - v * NP;
+        const int e = e0 + r;
+        bool forced = false;
+        for (int j = 0; j < na.n_out; ++j) forced = forced || na.out_var[j] == v;
+        if (e < T.E && !forced) gmem(T.out)[v * vs + (size_t)e * NP + n] = 0.0;
+    }
+}
+
+// The layers of one 16-row block: bufA holds the rows' normalised bf16
+// inputs (zero beyond dims[0] and for rows past the target's end), bufB is
+// scratch of the same shape; hidden layers apply bias and activation, the
+// last layer de-normalises and writes (or adds) s for rows e0 .. e0 + 15 of
+// T.  Ends with a block barrier.
+__device__ __forceinline__ void net_block_forward(const NetArgs& na, int NP, const NetTarget& T, int e0, int accumulate,
+                                                  uint16_t* bufA, uint16_t* bufB, int ld, int wave, int lane) {
+    const size_t vs = (size_t)T.E * NP;
+    const int L = na.n_layers;
+    for (int l = 0; l < L; ++l) {
+        const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
+        const global_t<const float>* bias = gmem(na.b[l]);
+        if (l < L - 1) {
+            const int act = na.act;
+            tile_mma(bufA, ld, gmem(na.W[l]), Kp, Np, wave, lane, [&](int m, int n, float v) {
+                const float z = v + (n < Nd ? bias[n] : 0.0f);
+                bufB[m * ld + n] = f2bf(n < Nd ? act_fwd(z, act) : 0.0f);
+            });
+        } else {
+            tile_mma(bufA, ld, gmem(na.W[l]), Kp, Np, wave, lane, [&](int m, int n, float v) {
+                const int e = e0 + m;
+                if (e < T.E && n < Nd) {
+                    const float y = v + bias[n];
+                    const int j = n / NP, node = n - j * NP;
+                    const int vv = na.out_var[j];
+                    const int cc = vv * NP + node;
+                    const double s = na.col ? na.mask[vv] * (na.col[15 * NP + cc] * (double)y + na.col[10 * NP + cc])
+                                            : na.mask[vv] * (na.sig_out[vv] * (double)y + na.mu_out[vv]);
+                    global_t<double>* o = gmem(T.out) + vv * vs + (size_t)e * NP + node;
+                    *o = accumulate ? *o + s : s;
+                }
+            });
+        }
+        __syncthreads();
+        uint16_t* tmp = bufA;
+        bufA = bufB;
+        bufB = tmp;
+    }
+}
+
+}  // namespace dgnn

@@ -39,5 +39,11 @@ int net_forcing_impl(const nn_model* m, const Mesh& mesh, const double* q, doubl
                      hipStream_t st);
 // batched: several solves' fields in one launch (all on meshes of the same order)
 int net_forcing_batch(const nn_model* m, int n_p, const NetTarget* targets, int nt, hipStream_t st);
+// whether the stage's BR1 pass and the network (write mode, out = s(q)) can
+// run as one launch (launch_grad_net) on this mesh
+bool grad_net_fusable(const nn_model* m, const Mesh& mesh);
+// the BR1 pass of the stage described by dl and out = s(q) in one launch
+int grad_net_impl(const nn_model* m, const Mesh& mesh, const DescList& dl, const double* q, double* out,
+                  hipStream_t st);
 
 }  // namespace dgnn

@@ -14,102 +14,11 @@
 // transposed activations and output gradients needed by the weight-gradient
 // products dW_l = dz_l^T h_l, which reduce over the batch in a second kernel
 // (split over the batch, then a fixed-order sum).
-#include "dgnn_internal.hpp"
+#include "nn_device.hpp"
 
 namespace dgnn {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-// Global-memory views of pointers taken from the argument structs: indexed
-// by a run-time layer number they reach the kernel as generic pointers, and
-// generic (flat) accesses count against the LDS counter as well, so LDS
-// accesses would wait for the global traffic in flight.
-template <class T>
-using global_t = __attribute__((address_space(1))) T;
-template <class T>
-__device__ __forceinline__ global_t<T>* gmem(T* p) { return (global_t<T>*)p; }
-
-constexpr int kRows = 16;      // rows (elements / samples) per block
-constexpr int kThreads = 256;     // weight-gradient blocks: four wavefronts, one tile each
-constexpr int kRowWaves = 16;     // row-block kernels: sixteen wavefronts share the column tiles
-constexpr int kRowThreads = 64 * kRowWaves;
-constexpr int kLdPad = 8;      // LDS row padding (bf16 elements)
-
 int net_rows_per_block() { return kRows; }
-
-// float32 -> bfloat16, round to nearest even (NaN kept quiet)
-__device__ __forceinline__ uint16_t f2bf(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x0040u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
-__device__ __forceinline__ float act_fwd(float z, int act) { return act == 0 ? tanhf(z) : fmaxf(z, 0.0f); }
-// derivative through the output h = act(z)
-__device__ __forceinline__ float act_bwd(float h, int act) { return act == 0 ? 1.0f - h * h : (h > 0.0f ? 1.0f : 0.0f); }
-
-// C[16][Np] = A[16][Kp] W^T with W [Np][Kp] row-major bf16 in global memory.
-// Wave w computes the 16-column tiles w, w + kRowWaves, ...; epi(m, n, value)
-// per output.  For the common widths the K loop is unrolled so that all of a
-// tile's weight fragments are in flight at once: the weights come from L2 and
-// their latency, not the matrix cores, bounds this product, so sixteen
-// wavefronts (one or two tiles each) beat fewer wavefronts with prefetching.
-template <int KP, class Epi>
-__device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, int ldA,
-                                               const global_t<uint16_t>* __restrict__ W, int Np, int wave, int lane,
-                                               Epi& epi) {
-    constexpr int KS = KP / 32;
-    const int kq = 8 * (lane >> 4);
-    const int r = lane & 15;
-    const uint16_t* arow = sA + r * ldA + kq;
-    for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
-        const global_t<uint16_t>* wrow = W + (size_t)(tile * 16 + r) * KP + kq;
-        bf16x8 b[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) b[s] = *(const global_t<bf16x8>*)(wrow + 32 * s);
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const bf16x8 a = *(const bf16x8*)(arow + 32 * s);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], acc, 0, 0, 0);
-        }
-        const int n = tile * 16 + r;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) epi(4 * (lane >> 4) + i, n, acc[i]);
-    }
-}
-
-template <class Epi>
-__device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ldA,
-                                         const global_t<uint16_t>* __restrict__ W, int Kp, int Np, int wave, int lane,
-                                         Epi epi) {
-    if (Kp == 256) {
-        tile_mma_fixed<256>(sA, ldA, W, Np, wave, lane, epi);
-        return;
-    }
-    if (Kp == 320) {
-        tile_mma_fixed<320>(sA, ldA, W, Np, wave, lane, epi);
-        return;
-    }
-    const int kq = 8 * (lane >> 4);
-    const int r = lane & 15;
-    for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int n = tile * 16 + r;
-        const global_t<uint16_t>* wrow = W + (size_t)n * Kp + kq;
-        const uint16_t* arow = sA + r * ldA + kq;
-        for (int k0 = 0; k0 < Kp; k0 += 32) {
-            const bf16x8 a = *(const bf16x8*)(arow + k0);
-            const bf16x8 b = *(const global_t<bf16x8>*)(wrow + k0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) epi(4 * (lane >> 4) + i, n, acc[i]);
-    }
-}
 
 struct NetTargets {
     NetTarget t[16];
@@ -146,59 +55,13 @@ __global__ void __launch_bounds__(kRowThreads) k_net_forcing(NetArgs na, int NP,
         if (e < E && c < din) {
             const int j = c / NP, n = c - j * NP;
             const int v = na.in_var[j];
-            const double qv = T.q[v * vs + (size_t)e * NP + n];
-            if (na.col) {
-                const int cc = v * NP + n;
-                x = (float)((qv - na.col[cc]) / na.col[5 * NP + cc]);
-            } else {
-                x = (float)((qv - na.mu_in[v]) / na.sig_in[v]);
-            }
+            x = net_input(na, NP, v, n, gmem(T.q)[v * vs + (size_t)e * NP + n]);
         }
         bufA[r * ld + c] = f2bf(x);
     }
-    // write mode: the variables the network does not force get s = 0
-    if (!accumulate && na.n_out < 5) {
-        for (int idx = t; idx < kRows * 5 * NP; idx += kRowThreads) {
-            const int r = idx / (5 * NP), c = idx - r * (5 * NP);
-            const int v = c / NP, n = c - v * NP;
-            const int e = e0 + r;
-            bool forced = false;
-            for (int j = 0; j < na.n_out; ++j) forced = forced || na.out_var[j] == v;
-            if (e < E && !forced) T.out[v * vs + (size_t)e * NP + n] = 0.0;
-        }
-    }
+    if (!accumulate) net_zero_unforced(na, NP, T, e0, t);
     __syncthreads();
-
-    const int L = na.n_layers;
-    for (int l = 0; l < L; ++l) {
-        const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
-        const global_t<const float>* bias = gmem(na.b[l]);
-        if (l < L - 1) {
-            const int act = na.act;
-            tile_mma(bufA, ld, gmem(na.W[l]), Kp, Np, wave, lane, [&](int m, int n, float v) {
-                const float z = v + (n < Nd ? bias[n] : 0.0f);
-                bufB[m * ld + n] = f2bf(n < Nd ? act_fwd(z, act) : 0.0f);
-            });
-        } else {
-            tile_mma(bufA, ld, gmem(na.W[l]), Kp, Np, wave, lane, [&](int m, int n, float v) {
-                const int e = e0 + m;
-                if (e < E && n < Nd) {
-                    const float y = v + bias[n];
-                    const int j = n / NP, node = n - j * NP;
-                    const int vv = na.out_var[j];
-                    const int cc = vv * NP + node;
-                    const double s = na.col ? na.mask[vv] * (na.col[15 * NP + cc] * (double)y + na.col[10 * NP + cc])
-                                            : na.mask[vv] * (na.sig_out[vv] * (double)y + na.mu_out[vv]);
-                    double* o = T.out + vv * vs + (size_t)e * NP + node;
-                    *o = accumulate ? *o + s : s;
-                }
-            });
-        }
-        __syncthreads();
-        uint16_t* tmp = bufA;
-        bufA = bufB;
-        bufB = tmp;
-    }
+    net_block_forward(na, NP, T, e0, accumulate, bufA, bufB, ld, wave, lane);
 }
 
 // ------------------------------------------------------------------- weights

@@ -242,7 +242,8 @@ def test_profiled_corrected_steps_equal_plain_steps(B):
     prof = B.dg_profile_steps(m, q2, k2, dt, 3, model=model)
     torch.cuda.synchronize()
     assert torch.equal(q, q2) and torch.equal(k, k2)
-    assert prof["net"] > 0 and prof["grad"] > 0 and prof["resid"] > 0
+    # at P = 3 the BR1 pass and the network run as one launch, timed as "net"
+    assert prof["net"] > 0 and prof["grad"] == 0 and prof["resid"] > 0
 
 
 def test_diagnostics_and_error_norm(B):
