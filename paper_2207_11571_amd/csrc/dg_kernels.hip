@@ -576,23 +576,24 @@ __device__ __forceinline__ void grad_volume_form(const DescList& dl) {
 // face's edges.  The result equals the face interpolation of the volume
 // gradient up to rounding, at O(P^3) instead of O(P^4) work per element.
 template <int PP>
-__device__ __forceinline__ void grad_face_form(const DescList& dl) {
+struct GradFaceLds {
+    static constexpr int NET = 24 * PP;          // edge tasks: 6 faces x 2 tangential axes x 2 sides x PP
+    static constexpr int N = 5 * Shape<PP>::NP + 48 * Shape<PP>::NF + 4 * NET;
+};
+
+// element e of solve D, thread t, basis B, LDS area sh of GradFaceLds<PP>::N
+template <int PP>
+__device__ __forceinline__ void grad_face_element(const SolveDesc& D, int e, int t, const BasisTab& B,
+                                                  double* __restrict__ sh) {
     using S = Shape<PP>;
     constexpr int NP = S::NP, NF = S::NF;
-    constexpr int NET = 24 * PP;                 // edge tasks: 6 faces x 2 tangential axes x 2 sides x PP
-    __shared__ double sh[5 * NP + 48 * NF + 4 * NET];
+    constexpr int NET = GradFaceLds<PP>::NET;
     double* what = sh + 5 * NP;                  // [6][4][NF] common BR1 values
     double* wf = what + 24 * NF;                 // [6][4][NF] face traces of w
     double* edge = wf + 24 * NF;                 // [6][2][2][4][PP] lifting values at the face edges
-    const int b = blockIdx.x;
-    const int si = find_solve(dl, b);
-    const SolveDesc& D = *dl.d[si];
     const Phys ph = D.ph;
-    const int e = b - dl.blk[si];
     const int ecx = e % D.N, ecy = (e / D.N) % D.N, ecz = e / (D.N * D.N);
     const int E = D.E;
-    const int t = threadIdx.x;
-    const BasisTab& B = c_basis[PP - 2];
 
     double qn[5];
     if (t < NP) {
@@ -731,6 +732,14 @@ __device__ __forceinline__ void grad_face_form(const DescList& dl) {
 // element.  The face form does less arithmetic but more index work per face
 // node; measured, it is the faster one at P = 8 only.
 template <int PP>
+__device__ __forceinline__ void grad_face_form(const DescList& dl) {
+    __shared__ double sh[GradFaceLds<PP>::N];
+    const int b = blockIdx.x;
+    const int si = find_solve(dl, b);
+    grad_face_element<PP>(*dl.d[si], b - dl.blk[si], threadIdx.x, c_basis[PP - 2], sh);
+}
+
+template <int PP>
 __global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::GRAD_WPE)))
 k_grad(DescList dl) {
     if constexpr (PP >= 9) grad_face_form<PP>(dl);
@@ -778,29 +787,28 @@ __global__ void __launch_bounds__(kRowThreads) k_grad_net(DescList dl, NetArgs n
     net_block_forward(na, NP, T, e0, 0, bufA, bufB, ld, wave, lane);
 }
 
-// Residual (update == 0: out = p(q) + forcing) or Runge-Kutta stage
-// (update == 1: k <- A k + dt R, q <- q + B k, traces of the new q).
-template <int PP, int UPDATE>
-__global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::WPE)))
-k_resid(DescList dl, double rkA, double rkB, int first_stage) {
-    using S = Shape<PP>;
-    constexpr int NP = S::NP, NF = S::NF;
+template <int PP>
+struct ResidLds {
     // P = 8 (one block per CU): the three directions' node fluxes are
     // stored at once, so the flux divergence needs one barrier, not six
-    constexpr bool DIV3 = PP >= 9;
-    __shared__ double sh[(DIV3 ? 20 : 5) * NP + 54 * NF];
+    static constexpr bool DIV3 = PP >= 9;
+    static constexpr int N = (DIV3 ? 20 : 5) * Shape<PP>::NP + 54 * Shape<PP>::NF;
+};
+
+// element e of solve D, thread t of the element's Shape<PP>::NT, basis B,
+// LDS area sh of ResidLds<PP>::N doubles
+template <int PP, int UPDATE>
+__device__ __forceinline__ void resid_element(const SolveDesc& D, int e, int t, const BasisTab& B,
+                                              double* __restrict__ sh, double rkA, double rkB, int first_stage) {
+    using S = Shape<PP>;
+    constexpr int NP = S::NP, NF = S::NF;
+    constexpr bool DIV3 = ResidLds<PP>::DIV3;
     double* fhat = sh + (DIV3 ? 20 : 5) * NP;   // [6][5][NF] net interface flux
     double* G3 = sh + 5 * NP;                     // DIV3: [3][5][NP] node fluxes
     double* what = fhat + 30 * NF;       // [6][4][NF] common BR1 values
-    const int b = blockIdx.x;
-    const int si = find_solve(dl, b);
-    const SolveDesc& D = *dl.d[si];
     const Phys ph = D.ph;
-    const int e = b - dl.blk[si];
     const int ecx = e % D.N, ecy = (e / D.N) % D.N, ecz = e / (D.N * D.N);
     const int E = D.E;
-    const int t = threadIdx.x;
-    const BasisTab& B = c_basis[PP - 2];
     const size_t node = (size_t)e * NP + t;
     const size_t vstride = (size_t)E * NP;
 
@@ -971,6 +979,42 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     }
     __syncthreads();
     write_traces<PP>(sh, B, t, e, gmem(D.qtr_out));
+}
+
+// Residual (update == 0: out = p(q) + forcing) or Runge-Kutta stage
+// (update == 1: k <- A k + dt R, q <- q + B k, traces of the new q), one
+// element per block.
+template <int PP, int UPDATE>
+__global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::WPE)))
+k_resid(DescList dl, double rkA, double rkB, int first_stage) {
+    __shared__ double sh[ResidLds<PP>::N];
+    const int b = blockIdx.x;
+    const int si = find_solve(dl, b);
+    resid_element<PP, UPDATE>(*dl.d[si], b - dl.blk[si], threadIdx.x, c_basis[PP - 2], sh, rkA, rkB, first_stage);
+}
+
+// The same for one solve whose blocks fill a CU each (P = 8): one block per
+// CU walks the elements b, b + G, b + 2G, ... (G blocks), which spares the
+// launch of a block per element and lets each block's next element start as
+// soon as it is done with the last.  The descriptor is read once, at entry
+// (inside the loop, after the loop's own stores, the compiler could only
+// read it with vector loads that wait for those stores).
+template <int PP, int UPDATE>
+__global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::WPE)))
+k_resid_loop(DescList dl, double rkA, double rkB, int first_stage) {
+    __shared__ double sh[ResidLds<PP>::N];
+    const SolveDesc D = *dl.d[0];
+    for (int e = blockIdx.x; e < D.E; e += gridDim.x) {
+        // the thread index and the basis table made opaque per element, so
+        // that what derives from them (line and face indices, basis entries)
+        // is recomputed instead of being held in registers across the loop
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        int bz = 0;
+        asm volatile("" : "+s"(bz));
+        resid_element<PP, UPDATE>(D, e, t, c_basis[PP - 2 + bz], sh, rkA, rkB, first_stage);
+        __syncthreads();
+    }
 }
 
 // Taylor-Green vortex initial condition, Eq. (11), on [0, L]^3.
@@ -1255,6 +1299,20 @@ hipError_t launch_grad(int PPv, const DescList& dl, hipStream_t st) {
     return hipGetLastError();
 }
 
+// compute units of the current device (persistent launches size their grid
+// by it), looked up once per device
+static int cu_count() {
+    static int cus[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
+    if (cus[dev] <= 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
 hipError_t launch_grad_net(int PPv, const DescList& dl, const NetArgs& na, const NetTarget& T, hipStream_t st) {
     if (PPv != 4 || dl.n != 1 || T.E % kRows != 0 || na.dims[0] != na.n_in * 64) return hipErrorInvalidValue;
     int pmax = 0;
@@ -1271,6 +1329,16 @@ hipError_t launch_grad_net(int PPv, const DescList& dl, const NetArgs& na, const
 hipError_t launch_resid(int PPv, int update, const DescList& dl, double rkA, double rkB, int first_stage,
                         hipStream_t st) {
     const int nb = dl.blk[dl.n];
+    if (PPv == 9 && dl.n == 1) {
+        // one solve at P = 8: a block per CU (the block's LDS allows no
+        // second), each walking its share of the elements
+        const int grid = nb < cu_count() ? nb : cu_count();
+        if (update)
+            hipLaunchKernelGGL((k_resid_loop<9, 1>), dim3(grid), dim3(Shape<9>::NT), 0, st, dl, rkA, rkB, first_stage);
+        else
+            hipLaunchKernelGGL((k_resid_loop<9, 0>), dim3(grid), dim3(Shape<9>::NT), 0, st, dl, rkA, rkB, first_stage);
+        return hipGetLastError();
+    }
     if (update) {
         DG_DISPATCH_PP(PPv, hipLaunchKernelGGL((k_resid<PP, 1>), dim3(nb), dim3(Shape<PP>::NT), 0, st, dl, rkA, rkB,
                                                first_stage));
