@@ -792,7 +792,10 @@ struct ResidLds {
     // P = 8 (one block per CU): the three directions' node fluxes are
     // stored at once, so the flux divergence needs one barrier, not six
     static constexpr bool DIV3 = PP >= 9;
-    static constexpr int N = (DIV3 ? 20 : 5) * Shape<PP>::NP + 54 * Shape<PP>::NF;
+    // P = 5, 6: the x and y node fluxes at once (four barriers instead of
+    // six; the LDS still lets three blocks share a CU)
+    static constexpr bool DIV2 = PP >= 6 && PP <= 7;
+    static constexpr int N = (DIV3 ? 20 : (DIV2 ? 10 : 5)) * Shape<PP>::NP + 54 * Shape<PP>::NF;
 };
 
 // element e of solve D, thread t of the element's Shape<PP>::NT, basis B,
@@ -803,7 +806,8 @@ __device__ __forceinline__ void resid_element(const SolveDesc& D, int e, int t, 
     using S = Shape<PP>;
     constexpr int NP = S::NP, NF = S::NF;
     constexpr bool DIV3 = ResidLds<PP>::DIV3;
-    double* fhat = sh + (DIV3 ? 20 : 5) * NP;   // [6][5][NF] net interface flux
+    constexpr bool DIV2 = ResidLds<PP>::DIV2;
+    double* fhat = sh + (DIV3 ? 20 : (DIV2 ? 10 : 5)) * NP;   // [6][5][NF] net interface flux
     double* G3 = sh + 5 * NP;                     // DIV3: [3][5][NP] node fluxes
     double* what = fhat + 30 * NF;       // [6][4][NF] common BR1 values
     const Phys ph = D.ph;
@@ -922,6 +926,41 @@ __device__ __forceinline__ void resid_element(const SolveDesc& D, int e, int t, 
 #pragma unroll
             for (int v = 0; v < 5; ++v) R[v] -= dv[v];
             weak_deriv<PP, 2, 5>(G3 + 10 * NP, fhat, B, t, ph.s, dv);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) R[v] -= dv[v];
+        }
+    } else if constexpr (DIV2) {
+        __syncthreads();
+        if (t < NP) {
+            double G[5];
+            flux_net<0>(qn, ns, ph, G);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sh[v * NP + t] = G[v];
+            flux_net<1>(qn, ns, ph, G);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sh[(5 + v) * NP + t] = G[v];
+        }
+        __syncthreads();
+        if (t < NP) {
+            double dv[5];
+            weak_deriv<PP, 0, 5>(sh, fhat, B, t, ph.s, dv);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) R[v] -= dv[v];
+            weak_deriv<PP, 1, 5>(sh + 5 * NP, fhat, B, t, ph.s, dv);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) R[v] -= dv[v];
+        }
+        __syncthreads();
+        if (t < NP) {
+            double G[5];
+            flux_net<2>(qn, ns, ph, G);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sh[v * NP + t] = G[v];
+        }
+        __syncthreads();
+        if (t < NP) {
+            double dv[5];
+            weak_deriv<PP, 2, 5>(sh, fhat, B, t, ph.s, dv);
 #pragma unroll
             for (int v = 0; v < 5; ++v) R[v] -= dv[v];
         }
