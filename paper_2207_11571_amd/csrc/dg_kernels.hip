@@ -37,8 +37,9 @@ struct Shape {
     // minimum wavefronts per SIMD that the stage kernels are compiled for:
     // five lets three blocks of 4 - 6 wavefronts share a CU (P = 4 - 6;
     // P = 3 is bound by LDS, P >= 7 by the registers it needs), where the
-    // kernel fits the registers that leaves without spilling
-    static constexpr int WPE = (PP >= 5 && PP <= 7) ? 5 : 2;
+    // kernel fits the registers that leaves without spilling; the residual
+    // at P = 5 (x and y fluxes at once) needs more and runs four
+    static constexpr int WPE = (PP == 5 || PP == 7) ? 5 : (PP == 6 ? 4 : 2);
     static constexpr int GRAD_WPE = (PP >= 5 && PP <= 7) ? 5 : 2;
 };
 
@@ -829,6 +830,14 @@ __device__ __forceinline__ void resid_element(const SolveDesc& D, int e, int t, 
 #pragma unroll
             for (int v = 0; v < 5; ++v) kp[v] = gmem(D.k)[v * vstride + node];
         }
+        // the gradient variables go to LDS with the face phase's values,
+        // behind the same barrier
+        if (ph.viscous) {
+            double w[4];
+            gradient_vars(qn, ph.gm1, w);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sh[c * NP + t] = w[c];
+        }
     }
 
 #pragma unroll
@@ -881,13 +890,15 @@ __device__ __forceinline__ void resid_element(const SolveDesc& D, int e, int t, 
     }
     double g[3][4];
     if (ph.viscous) {
-        if (t < NP) {
-            double w[4];
-            gradient_vars(qn, ph.gm1, w);
+        if (!QEARLY) {
+            if (t < NP) {
+                double w[4];
+                gradient_vars(qn, ph.gm1, w);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) sh[c * NP + t] = w[c];
+                for (int c = 0; c < 4; ++c) sh[c * NP + t] = w[c];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (t < NP) {
             weak_deriv<PP, 0, 4>(sh, what, B, t, ph.s, g[0]);
             weak_deriv<PP, 1, 4>(sh, what, B, t, ph.s, g[1]);
@@ -1011,13 +1022,18 @@ __device__ __forceinline__ void resid_element(const SolveDesc& D, int e, int t, 
             gmem(D.q)[v * vstride + node] = qn[v];
         }
     }
-    if (!DIV3) __syncthreads();
+    // the new state goes to an LDS area no thread reads any more: the first
+    // five fields (DIV3: its node fluxes live above them), the x-y flux
+    // fields (DIV2: read before the z fluxes were written), else after a
+    // barrier
+    double* qs = DIV2 ? sh + 5 * NP : sh;
+    if (!DIV3 && !DIV2) __syncthreads();
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sh[v * NP + t] = qn[v];
+        for (int v = 0; v < 5; ++v) qs[v * NP + t] = qn[v];
     }
     __syncthreads();
-    write_traces<PP>(sh, B, t, e, gmem(D.qtr_out));
+    write_traces<PP>(qs, B, t, e, gmem(D.qtr_out));
 }
 
 // Residual (update == 0: out = p(q) + forcing) or Runge-Kutta stage
