@@ -286,6 +286,8 @@ def main():
         for (P, Re, Cs) in ((6, 1600.0, 0.0), (8, 1600.0, 0.0)):
             solve_case(B, torch, 16, P, Re, Cs, 5, 0)
         solve_case(B, torch, 16, 3, 200.0, 0.0, 5, 0, model=net_model(B, synthetic))
+        # the stand-alone network launch (the correction after each step)
+        solve_case(B, torch, 16, 3, 200.0, 0.0, 5, 0, model=net_model(B, synthetic), post=True)
         log("profile pass done")
         return
 
