@@ -658,7 +658,8 @@ __device__ __forceinline__ void grad_face_element(const SolveDesc& D, int e, int
 #pragma unroll
         for (int c = 0; c < 4; ++c) edge[(rest * 4 + c) * PP + r] = acc[c];
     }
-    __syncthreads();
+    // the face traces of w: independent of the edge values (both read only
+    // what the first barrier published), so no barrier between them
 #pragma unroll
     for (int r = 0; r < S::TPT; ++r) {
         const int tau = t + r * S::NT;
