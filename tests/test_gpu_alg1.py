@@ -204,23 +204,31 @@ def test_io_selection_rejects_bad_sizes(B):
         B.nn_forcing(model, m, m.field(1.0), m.field(0.0))
 
 
-def test_stage_forcing_with_momentum_network(B):
+@pytest.mark.parametrize("N,per_node", [(3, False), (4, False), (4, True)])
+def test_stage_forcing_with_momentum_network(B, N, per_node):
     """The per-stage corrected stepper (Eq. (4)) with a momentum-only network:
     the unforced variables get no forcing and the accumulated correction
-    matches the oracle's."""
+    matches the oracle's.  27 elements take the separate BR1 and network
+    launches, 64 the fused one (also with per-node maps)."""
     from oracle import dg, forcing, rk
-    say("per-stage forcing, momentum network")
-    N, P, Re, steps = 3, 3, 400.0, 10
+    say("per-stage forcing, momentum network", N, per_node)
+    P, Re, steps = 3, 400.0, 10
     layers = synthetic.mlp_init(DIMS, seed=4)
     layers = [(W, b + 0.02) for W, b in layers]
     params, norm = _oracle_model(layers)
+    model = B.Model(DIMS, B.pack_params(layers), NORM, activation="relu", train=False, in_vars=MOM, out_vars=MOM)
+    if per_node:
+        x, y = _rows(512, 22)
+        col = B.nn_column_stats(_to_gpu(x, np.float32), _to_gpu(y, np.float32), 64)
+        norm = forcing.Normalisation(norm.mu_in, norm.sigma_in, norm.mu_out, norm.sigma_out,
+                                     columns=[c for c in col.cpu().numpy()])
+        model.set_column_norm(col, 64)
     prm, q0 = _state(N, P, Re, seed=8)
     dt = dg.stable_dt(q0, prm)
     q_ref = rk.integrate(q0, dt, steps, lambda qq, t: forcing.corrected_rhs(qq, prm, params, norm, "relu",
                                                                             None, MOM, MOM))
     q_unc = rk.integrate(q0, dt, steps, lambda qq, t: dg.residual(qq, prm))
     m = B.Mesh(N, P, Re)
-    model = B.Model(DIMS, B.pack_params(layers), NORM, activation="relu", train=False, in_vars=MOM, out_vars=MOM)
     # leave garbage in the workspace's forcing buffer: the write must clear it
     m.ws.fill_(0x7F)
     q = _to_gpu(dg.to_flat(q0))
