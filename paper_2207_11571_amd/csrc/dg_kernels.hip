@@ -1358,9 +1358,11 @@ hipError_t launch_grad(int PPv, const DescList& dl, hipStream_t st) {
 // compute units of the current device (persistent launches size their grid
 // by it), looked up once per device
 static int cu_count() {
+    static std::mutex mu;
     static int cus[kMaxDevices] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
+    std::lock_guard<std::mutex> lk(mu);
     if (cus[dev] <= 0) {
         int n = 0;
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
@@ -1375,9 +1377,21 @@ hipError_t launch_grad_net(int PPv, const DescList& dl, const NetArgs& na, const
     for (int l = 0; l <= na.n_layers; ++l) pmax = pmax > na.pdims[l] ? pmax : na.pdims[l];
     const size_t smem = (size_t)kRowWaves * GradLds<4>::N * sizeof(double) +
                         (size_t)2 * kRows * (pmax + kLdPad) * sizeof(uint16_t);
-    hipError_t e = hipFuncSetAttribute((const void*)k_grad_net<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)smem);
+    // the dynamic LDS limit, raised once per device to the largest size asked
+    static std::mutex mu;
+    static size_t set_for[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (set_for[dev] < smem) {
+            e = hipFuncSetAttribute((const void*)k_grad_net<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+            if (e != hipSuccess) return e;
+            set_for[dev] = smem;
+        }
+    }
     hipLaunchKernelGGL(k_grad_net<4>, dim3(T.E / kRows), dim3(kRowThreads), smem, st, dl, na, T);
     return hipGetLastError();
 }
