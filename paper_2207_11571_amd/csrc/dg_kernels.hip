@@ -1357,7 +1357,7 @@ hipError_t launch_grad(int PPv, const DescList& dl, hipStream_t st) {
 
 // compute units of the current device (persistent launches size their grid
 // by it), looked up once per device
-static int cu_count() {
+int cu_count() {
     static std::mutex mu;
     static int cus[kMaxDevices] = {};
     int dev = 0;

@@ -136,6 +136,8 @@ hipError_t scratch_setup(int dev);
 void* scratch_device_ptr(int dev);
 hipError_t launch_write_descs(const SolveDesc* host, int n, SolveDesc* dev, hipStream_t st);
 hipError_t launch_traces(int PP, const DescList& dl, hipStream_t st);
+// compute units of the current device
+int cu_count();
 hipError_t launch_grad(int PP, const DescList& dl, hipStream_t st);
 // k_grad and the forcing network in one launch (P = 3, one solve, E a
 // multiple of 16, the network reading all n_p nodes of its variables);

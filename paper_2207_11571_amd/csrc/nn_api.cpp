@@ -100,8 +100,11 @@ int net_forcing_impl(const nn_model* m, const Mesh& mesh, const double* q, doubl
 }
 
 bool grad_net_fusable(const nn_model* m, const Mesh& mesh) {
+    // the fused launch pays off once its 16-element blocks fill the GPU (one
+    // per CU); on smaller meshes the separate BR1 launch spreads the
+    // elements over all CUs and wins
     return m && mesh.PP == 4 && mesh.ph.viscous && mesh.E % net_rows_per_block() == 0 &&
-           m->dims[0] == m->n_in * mesh.n_p;
+           mesh.E / net_rows_per_block() >= cu_count() && m->dims[0] == m->n_in * mesh.n_p;
 }
 
 int grad_net_impl(const nn_model* m, const Mesh& mesh, const DescList& dl, const double* q, double* out,

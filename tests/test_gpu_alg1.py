@@ -204,12 +204,12 @@ def test_io_selection_rejects_bad_sizes(B):
         B.nn_forcing(model, m, m.field(1.0), m.field(0.0))
 
 
-@pytest.mark.parametrize("N,per_node", [(3, False), (4, False), (4, True)])
+@pytest.mark.parametrize("N,per_node", [(3, False), (16, False), (16, True)])
 def test_stage_forcing_with_momentum_network(B, N, per_node):
     """The per-stage corrected stepper (Eq. (4)) with a momentum-only network:
     the unforced variables get no forcing and the accumulated correction
     matches the oracle's.  27 elements take the separate BR1 and network
-    launches, 64 the fused one (also with per-node maps)."""
+    launches, 16^3 the fused one (also with per-node maps)."""
     from oracle import dg, forcing, rk
     say("per-stage forcing, momentum network", N, per_node)
     P, Re, steps = 3, 400.0, 10

@@ -225,14 +225,16 @@ def test_profiled_steps_equal_plain_steps(B, P):
     assert prof["traces"] > 0 and prof["grad"] > 0 and prof["resid"] > 0 and prof["net"] == 0
 
 
-def test_profiled_corrected_steps_equal_plain_steps(B):
-    """The same with the forcing network at every stage (P = 3)."""
-    say("profiled corrected steps")
+@pytest.mark.parametrize("N", [8, 16])
+def test_profiled_corrected_steps_equal_plain_steps(B, N):
+    """The same with the forcing network at every stage (P = 3); on 16^3
+    elements the BR1 pass and the network run as one launch."""
+    say("profiled corrected steps", N)
     dims = [320, 256, 256, 256, 320]
     norm = [1.0, 0.0, 0.0, 0.0, synthetic.TGV_ENERGY_LEVEL, 0.01, 1.0, 1.0, 1.0, 1.0,
             0.0, 0.0, 0.0, 0.0, 0.0, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3]
     model = B.Model(dims, B.pack_params(synthetic.mlp_init(dims, seed=0)), norm, train=False)
-    m = B.Mesh(8, 3, 200.0)
+    m = B.Mesh(N, 3, 200.0)
     q = m.field()
     B.dg_init_tgv(m, q)
     dt = B.dg_stable_dt(m, q)
@@ -242,8 +244,9 @@ def test_profiled_corrected_steps_equal_plain_steps(B):
     prof = B.dg_profile_steps(m, q2, k2, dt, 3, model=model)
     torch.cuda.synchronize()
     assert torch.equal(q, q2) and torch.equal(k, k2)
-    # at P = 3 the BR1 pass and the network run as one launch, timed as "net"
-    assert prof["net"] > 0 and prof["grad"] == 0 and prof["resid"] > 0
+    assert prof["net"] > 0 and prof["resid"] > 0
+    # the fused launch is timed as "net"
+    assert (prof["grad"] == 0) if N == 16 else (prof["grad"] > 0)
 
 
 def test_diagnostics_and_error_norm(B):

@@ -132,6 +132,9 @@ def test_invalid_requests(B):
 
 
 SERVED = {"P3 forcing every stage": dict(Re=200.0, P=3, N=4, Cs=0.0, use_nn=True, after_step=False, t_end=0.03),
+          # 16^3: the library fuses the BR1 pass and the network, the server does not
+          "P3 forcing every stage, 16^3": dict(Re=200.0, P=3, N=16, Cs=0.0, use_nn=True, after_step=False,
+                                               t_end=0.004),
           "P3 correction after each step": dict(Re=200.0, P=3, N=4, Cs=0.0, use_nn=True, after_step=True,
                                                 t_end=0.03),
           "P6 plain": dict(Re=1600.0, P=6, N=3, Cs=0.0, use_nn=False, after_step=False, t_end=0.005),
