@@ -200,16 +200,29 @@ struct ParamMap {
     int din[kMaxLayers], dout[kMaxLayers], pin[kMaxLayers], pout[kMaxLayers];
     int n_layers;
 };
+// Adam step of the whole parameter vector (and the loss output, when loss is
+// not null), for the fused end-of-step launch
+struct AdamArgs {
+    float* p;
+    float* m;
+    float* v;
+    uint16_t* wbf;
+    float lr, b1, b2, eps, bc1, bc2;
+    const float* loss_part;
+    int n_loss;
+    float inv_count;
+    float* loss;
+};
 size_t train_smem_bytes(const NetArgs& na);
 hipError_t launch_train_rows(const NetArgs& na, const TrainArgs& ta, int nblocks, hipStream_t st);
-hipError_t launch_grads(const GradArgs& ga, hipStream_t st);
-hipError_t launch_loss_final(const float* part, int n, float inv_count, float* loss, hipStream_t st);
+// the split-K weight-gradient products alone, and then the gradient
+// reductions, the Adam update and the loss in one launch
+hipError_t launch_wgrad(const GradArgs& ga, hipStream_t st);
+hipError_t launch_reduce_adam(const GradArgs& ga, const ParamMap& pm, const AdamArgs& aa, hipStream_t st);
 hipError_t launch_data_stats(const float* x, const float* y, int64_t rows, int n_p, double* part, int nblocks,
                              double* out_dev, hipStream_t st);
 hipError_t launch_column_stats(const float* x, const float* y, int64_t rows, int ncols, double* part, int nblocks,
                                double* out_dev, hipStream_t st);
-hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t n, const ParamMap& pm,
-                       uint16_t* wbf, float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st);
 
 // error reporting (thread-local)
 int set_error(int code, const char* fmt, ...);

@@ -360,10 +360,7 @@ int nn_train_step(nn_model* m, const float* x, const float* y, const int32_t* id
         ga.tblk[l + 1] = ga.tblk[l] + (ntiles + 3) / 4;
         ga.rblk[l + 1] = ga.rblk[l] + (ga.dout[l] * ga.din[l] + 255) / 256;
     }
-    NN_HIP(launch_grads(ga, st));
-    if (loss_dev)
-        NN_HIP(launch_loss_final(ta.loss_part, nblocks, (float)(1.0 / ((double)batch * m->dims[m->n_layers])),
-                                 loss_dev, st));
+    NN_HIP(launch_wgrad(ga, st));
     m->step += 1;
     const double bc1 = 1.0 - std::pow(0.9, (double)m->step);
     const double bc2 = 1.0 - std::pow(0.999, (double)m->step);
@@ -380,8 +377,22 @@ int nn_train_step(nn_model* m, const float* x, const float* y, const int32_t* id
         pm.pin[l] = m->pdims[l];
         pm.pout[l] = m->pdims[l + 1];
     }
-    NN_HIP(launch_adam(m->params, m->grad, m->adam_m, m->adam_v, m->n_params, pm, m->wbf, lr, 0.9f, 0.999f, 1e-7f,
-                       (float)bc1, (float)bc2, st));
+    AdamArgs aa;
+    aa.p = m->params;
+    aa.m = m->adam_m;
+    aa.v = m->adam_v;
+    aa.wbf = m->wbf;
+    aa.lr = lr;
+    aa.b1 = 0.9f;
+    aa.b2 = 0.999f;
+    aa.eps = 1e-7f;
+    aa.bc1 = (float)bc1;
+    aa.bc2 = (float)bc2;
+    aa.loss_part = ta.loss_part;
+    aa.n_loss = nblocks;
+    aa.inv_count = (float)(1.0 / ((double)batch * m->dims[m->n_layers]));
+    aa.loss = loss_dev;
+    NN_HIP(launch_reduce_adam(ga, pm, aa, st));
     return DG_OK;
 }
 

@@ -272,76 +272,82 @@ __global__ void __launch_bounds__(kThreads) k_wgrad(GradArgs ga) {
                 o[(size_t)(to * 32 + 16 * i + 4 * (lane >> 4) + v) * pin + tii * 32 + 16 * j + r] = acc[i][j][v];
 }
 
-// grad W_l = sum of the split-K partials, every layer in one launch, each
-// sum in a fixed order
-__global__ void __launch_bounds__(256) k_grad_reduce(GradArgs ga) {
+// Adam update of parameter i (flat index) with gradient gi; weights also go
+// to their bf16 copies W_l [pout][pin] and W_l^T [pin][pout]
+__device__ __forceinline__ void adam_one(const AdamArgs& aa, const ParamMap& pm, int64_t i, float gi) {
+    const float mi = aa.b1 * aa.m[i] + (1.0f - aa.b1) * gi;
+    const float vi = aa.b2 * aa.v[i] + (1.0f - aa.b2) * gi * gi;
+    aa.m[i] = mi;
+    aa.v[i] = vi;
+    const float pi = aa.p[i] - aa.lr * (mi / aa.bc1) / (sqrtf(vi / aa.bc2) + aa.eps);
+    aa.p[i] = pi;
     int l = 0;
-    while (l + 1 < ga.n_layers && (int)blockIdx.x >= ga.rblk[l + 1]) ++l;
-    const int idx = ((int)blockIdx.x - ga.rblk[l]) * 256 + threadIdx.x;
-    const int dout = ga.dout[l], din = ga.din[l], pout = ga.pout[l], pin = ga.pin[l];
-    if (idx < dout * din) {
-        const int o = idx / din, i = idx - o * din;
+    while (l + 1 < pm.n_layers && i >= pm.woff[l + 1]) ++l;
+    if (i < pm.boff[l]) {
+        const int64_t w = i - pm.woff[l];
+        const int o = (int)(w / pm.din[l]), ii = (int)(w - (int64_t)o * pm.din[l]);
+        const uint16_t h = f2bf(pi);
+        aa.wbf[pm.wbo[l] + (int64_t)o * pm.pin[l] + ii] = h;
+        aa.wbf[pm.wtbo[l] + (int64_t)ii * pm.pout[l] + o] = h;
+    }
+}
+
+// The end of a training step in one launch: blocks [0, rblk[L]) sum the
+// split-K weight-gradient partials, one thread per weight in a fixed order,
+// write the gradient and update that weight (Adam); the next ceil(nbias / 4)
+// blocks sum the bias row-block sums, one wavefront per bias (lane-strided
+// sums, then a fixed butterfly), and lane 0 updates that bias; with a loss
+// output, one more block sums the loss partials.  The same sums in the same
+// order as separate reduction launches would make, one launch instead of four.
+__global__ void __launch_bounds__(256) k_reduce_adam(GradArgs ga, ParamMap pm, AdamArgs aa, int nbias) {
+    const int wblk = ga.rblk[ga.n_layers];
+    const int bblk = (nbias + 3) / 4;
+    const int b = blockIdx.x;
+    if (b < wblk) {
+        int l = 0;
+        while (l + 1 < ga.n_layers && b >= ga.rblk[l + 1]) ++l;
+        const int idx = (b - ga.rblk[l]) * 256 + threadIdx.x;
+        const int dout = ga.dout[l], din = ga.din[l], pout = ga.pout[l], pin = ga.pin[l];
+        if (idx < dout * din) {
+            const int o = idx / din, i = idx - o * din;
+            float s = 0.0f;
+            for (int k = 0; k < ga.nks; ++k) s += gmem(ga.part[l])[(size_t)k * pout * pin + (size_t)o * pin + i];
+            gmem(ga.gW[l])[idx] = s;
+            adam_one(aa, pm, pm.woff[l] + idx, s);
+        }
+        return;
+    }
+    if (b < wblk + bblk) {
+        const int w = (b - wblk) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+        if (w >= nbias) return;
+        int l = 0, o = w;
+        while (l + 1 < ga.n_layers && o >= ga.dout[l]) {
+            o -= ga.dout[l];
+            ++l;
+        }
+        const int pout = ga.pout[l];
         float s = 0.0f;
-        for (int k = 0; k < ga.nks; ++k) s += ga.part[l][(size_t)k * pout * pin + (size_t)o * pin + i];
-        ga.gW[l][idx] = s;
-    }
-}
-
-// grad b_l = sum of the row-block sums of dz_l: one wavefront per bias
-// entry, lane-strided partial sums, then a fixed butterfly over the lanes
-__global__ void __launch_bounds__(256) k_bias_reduce(GradArgs ga, int nbias) {
-    const int w = (int)blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (w >= nbias) return;
-    int l = 0, o = w;
-    while (l + 1 < ga.n_layers && o >= ga.dout[l]) {
-        o -= ga.dout[l];
-        ++l;
-    }
-    const int pout = ga.pout[l];
-    float s = 0.0f;
-    for (int k = lane; k < ga.nrb; k += 64) s += ga.bias_part[l][(size_t)k * pout + o];
+        for (int k = lane; k < ga.nrb; k += 64) s += gmem(ga.bias_part[l])[(size_t)k * pout + o];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) ga.gb[l][o] = s;
-}
-
-__global__ void __launch_bounds__(256) k_loss_final(const float* __restrict__ part, int n, float inv_count,
-                                                   float* __restrict__ loss) {
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) {
+            gmem(ga.gb[l])[o] = s;
+            adam_one(aa, pm, pm.boff[l] + o, s);
+        }
+        return;
+    }
+    // the loss: sum of the row-block partials
     __shared__ float red[256];
     const int t = threadIdx.x;
     float s = 0.0f;
-    for (int i = t; i < n; i += 256) s += part[i];
+    for (int i = t; i < aa.n_loss; i += 256) s += aa.loss_part[i];
     red[t] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) red[t] += red[t + w];
         __syncthreads();
     }
-    if (t == 0) loss[0] = red[0] * inv_count;
-}
-
-__global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                                             float* __restrict__ v, int64_t n, ParamMap pm, uint16_t* __restrict__ wbf,
-                                             float lr, float b1, float b2, float eps, float bc1, float bc2) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const float gi = g[i];
-        const float mi = b1 * m[i] + (1.0f - b1) * gi;
-        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-        m[i] = mi;
-        v[i] = vi;
-        const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-        p[i] = pi;
-        // weights also go to their bf16 copies W_l [pout][pin] and W_l^T [pin][pout]
-        int l = 0;
-        while (l + 1 < pm.n_layers && i >= pm.woff[l + 1]) ++l;
-        if (i < pm.boff[l]) {
-            const int64_t w = i - pm.woff[l];
-            const int o = (int)(w / pm.din[l]), ii = (int)(w - (int64_t)o * pm.din[l]);
-            const uint16_t h = f2bf(pi);
-            wbf[pm.wbo[l] + (int64_t)o * pm.pin[l] + ii] = h;
-            wbf[pm.wtbo[l] + (int64_t)ii * pm.pout[l] + o] = h;
-        }
-    }
+    if (t == 0) aa.loss[0] = red[0] * aa.inv_count;
 }
 
 // Per-variable statistics of a training set (rows of 5 n_p floats).  Pass 0
@@ -526,26 +532,16 @@ hipError_t launch_train_rows(const NetArgs& na, const TrainArgs& ta, int nblocks
     return hipGetLastError();
 }
 
-hipError_t launch_grads(const GradArgs& ga, hipStream_t st) {
+hipError_t launch_wgrad(const GradArgs& ga, hipStream_t st) {
     hipLaunchKernelGGL(k_wgrad, dim3(ga.tblk[ga.n_layers], ga.nks), dim3(kThreads), 0, st, ga);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(ga.rblk[ga.n_layers]), dim3(256), 0, st, ga);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_adam(const GradArgs& ga, const ParamMap& pm, const AdamArgs& aa, hipStream_t st) {
     int nbias = 0;
     for (int l = 0; l < ga.n_layers; ++l) nbias += ga.dout[l];
-    hipLaunchKernelGGL(k_bias_reduce, dim3((nbias + 3) / 4), dim3(256), 0, st, ga, nbias);
-    return hipGetLastError();
-}
-
-hipError_t launch_loss_final(const float* part, int n, float inv_count, float* loss, hipStream_t st) {
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, n, inv_count, loss);
-    return hipGetLastError();
-}
-
-hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t n, const ParamMap& pm,
-                       uint16_t* wbf, float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st) {
-    int blocks = (int)((n + 255) / 256);
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, st, params, grad, m, v, n, pm, wbf, lr, b1, b2, eps, bc1,
-                       bc2);
+    const int blocks = ga.rblk[ga.n_layers] + (nbias + 3) / 4 + (aa.loss ? 1 : 0);
+    hipLaunchKernelGGL(k_reduce_adam, dim3(blocks), dim3(256), 0, st, ga, pm, aa, nbias);
     return hipGetLastError();
 }
 
