@@ -325,29 +325,44 @@ static int step_group(solve_server* S, int PP, std::vector<Solve*>& v, hipStream
     return DG_OK;
 }
 
-// Steps of one round for each order group: the costliest group (by nodes
-// per step) takes kChunk steps, cheaper groups proportionally more (up to
-// kChunkMax), so that a round takes about the same time on every stream;
-// never past any solve's last step or its KE-record capacity.
-static std::map<int, int64_t> round_plan(const std::map<int, std::vector<Solve*>>& groups) {
+// cost of one step of a solve, in node-stage units (the network adds about
+// as much again at every stage, less when it corrects once per step)
+static double step_cost(const Solve* s) {
+    return (double)s->mesh.E * s->mesh.n_p * (s->nn_active ? (s->req.nn_after_step ? 1.3 : 2.0) : 1.0);
+}
+
+// Steps of one round for each running solve.  Per order group, the group's
+// costliest solve takes n_g steps, where the costliest group (by summed cost
+// per step) takes kChunk and cheaper groups proportionally more, up to
+// kChunkMax, so that a round takes about the same time on every stream.
+// Within a group every solve gets about the same device time as that
+// costliest one: a solve whose steps cost a k-th as much takes k times the
+// steps (up to kChunkMax), so that a small solve batched with large ones of
+// its order does not wait for as many of their steps as it needs of its own.
+// Never past a solve's last step or its KE-record capacity.
+static std::map<const Solve*, int64_t> round_plan(const std::map<int, std::vector<Solve*>>& groups) {
     std::map<int, double> cost;
     double cmax = 0.0;
     for (auto& g : groups) {
         double c = 0.0;
-        for (Solve* s : g.second)
-            c += (double)s->mesh.E * s->mesh.n_p * (s->nn_active ? (s->req.nn_after_step ? 1.3 : 2.0) : 1.0);
+        for (Solve* s : g.second) c += step_cost(s);
         cost[g.first] = c;
         cmax = std::max(cmax, c);
     }
-    std::map<int, int64_t> plan;
+    std::map<const Solve*, int64_t> plan;
     for (auto& g : groups) {
-        int64_t n = (int64_t)std::min((double)kChunkMax, std::floor(kChunk * cmax / std::max(1.0, cost[g.first])));
-        n = std::max<int64_t>(n, 1);
+        const double ng = std::max(1.0, std::min((double)kChunkMax,
+                                                 std::floor(kChunk * cmax / std::max(1.0, cost[g.first]))));
+        double cbig = 0.0;
+        for (Solve* s : g.second) cbig = std::max(cbig, step_cost(s));
         for (Solve* s : g.second) {
-            n = std::min<int64_t>(n, s->n_steps - s->steps);
-            n = std::min<int64_t>(n, (int64_t)(kHist - 1 - (int)s->pending_t.size()) * s->req.ke_every);
+            double n = std::floor(ng * cbig / std::max(1.0, step_cost(s)));
+            n = std::min(n, std::max(ng, (double)kChunkMax));
+            int64_t k = std::max<int64_t>((int64_t)n, 1);
+            k = std::min<int64_t>(k, s->n_steps - s->steps);
+            k = std::min<int64_t>(k, (int64_t)(kHist - 1 - (int)s->pending_t.size()) * s->req.ke_every);
+            plan[s] = std::max<int64_t>(k, 1);
         }
-        plan[g.first] = std::max<int64_t>(n, 1);
     }
     return plan;
 }
@@ -464,13 +479,14 @@ static void server_loop(solve_server* S) {
         }
         std::map<int, std::vector<Solve*>> groups;
         for (Solve* s : run) groups[s->mesh.PP].push_back(s);
-        const std::map<int, int64_t> plan = round_plan(groups);
+        const std::map<const Solve*, int64_t> plan = round_plan(groups);
         const double t0 = now_s();
         int rc = DG_OK;
         int64_t steps_done = 0;
         for (auto& g : groups) {
             hipStream_t gst = S->gst[g.first];
-            const int64_t n_g = plan.at(g.first);
+            int64_t n_g = 0;
+            for (Solve* s : g.second) n_g = std::max(n_g, plan.at(s));
             // corrected solves: copy of the (already judged) state the round starts from
             for (Solve* s : g.second)
                 if (s->nn_active && rc == DG_OK) {
@@ -479,7 +495,14 @@ static void server_loop(solve_server* S) {
                                        hipMemcpyDeviceToDevice, gst) != hipSuccess)
                         rc = set_error(DG_EHIP, "state copy failed");
                 }
-            for (int64_t n = 0; n < n_g && rc == DG_OK; ++n) rc = step_group(S, g.first, g.second, gst);
+            // step n batches every solve that still has steps in this round
+            std::vector<Solve*> active;
+            for (int64_t n = 0; n < n_g && rc == DG_OK; ++n) {
+                active.clear();
+                for (Solve* s : g.second)
+                    if (plan.at(s) > n) active.push_back(s);
+                rc = step_group(S, g.first, active, gst);
+            }
             for (Solve* s : g.second)
                 if (s->nn_active && rc == DG_OK) rc = diag_impl(s->mesh, s->q, s->health, s->ws, gst);
             steps_done = std::max(steps_done, n_g);
