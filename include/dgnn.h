@@ -196,7 +196,8 @@ int dg_increment_target(const dg_mesh* hi, const dg_mesh* lo, double* q_hi, doub
  * Hidden activation: 0 = tanh, 1 = relu; the output layer is linear.
  * Parameters (caller-owned, device, float32) are packed layer by layer as
  * W_l[out][in] row-major followed by b_l[out].  The library keeps bfloat16
- * copies of the weights (w_bf16, caller-owned, nn_query's n_bf16 elements)
+ * copies of the weights (w_bf16, caller-owned, nn_query's n_bf16 elements,
+ * in the matrix cores' operand order, which the caller does not rely on)
  * for the matrix cores; biases stay float32.
  * norm (host, copied): mu_in[5], sigma_in[5], mu_out[5], sigma_out[5]:
  *   xhat = (x - mu_in[v]) / sigma_in[v],  s = mask[v] (sigma_out[v] yhat + mu_out[v]).

@@ -40,7 +40,20 @@ __device__ __forceinline__ float act_fwd(float z, int act) { return act == 0 ? t
 // derivative through the output h = act(z)
 __device__ __forceinline__ float act_bwd(float h, int act) { return act == 0 ? 1.0f - h * h : (h > 0.0f ? 1.0f : 0.0f); }
 
-// C[16][Np] = A[16][Kp] W^T with W [Np][Kp] row-major bf16 in global memory.
+// Position of W[n][k] (n < Np, k < Kp, both padded to multiples of 32) in
+// the bf16 weight copies: the fragment order of the B operand of
+// v_mfma_f32_16x16x32_bf16 as tile_mma loads it.  Each 16-column tile and
+// 32-wide K step is one 1 KB block in which lane r + 16 q holds
+// W[16 tile + r][32 s + 8 q, + 8), so that a wavefront's fragment load reads
+// one contiguous kilobyte instead of 64-byte pieces of sixteen rows (half
+// the time of a row-major layout for the chain of layers, measured).
+__host__ __device__ __forceinline__ int64_t wfrag_index(int n, int k, int Kp) {
+    const int tile = n >> 4, r = n & 15, s = k >> 5, q = (k & 31) >> 3, j = k & 7;
+    return ((((int64_t)tile * (Kp >> 5) + s) * 64 + r + 16 * q) << 3) + j;
+}
+
+// C[16][Np] = A[16][Kp] W^T with W [Np][Kp] bf16 in global memory, in the
+// fragment order of wfrag_index.
 // Wave w computes the 16-column tiles w, w + kRowWaves, ...; epi(m, n, value)
 // per output.  For the common widths the K loop is unrolled so that all of a
 // tile's weight fragments are in flight at once: the weights come from L2 and
@@ -55,10 +68,10 @@ __device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, 
     const int r = lane & 15;
     const uint16_t* arow = sA + r * ldA + kq;
     for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
-        const global_t<uint16_t>* wrow = W + (size_t)(tile * 16 + r) * KP + kq;
+        const global_t<uint16_t>* wt = W + ((int64_t)tile * KS * 64 + lane) * 8;
         bf16x8 b[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) b[s] = *(const global_t<bf16x8>*)(wrow + 32 * s);
+        for (int s = 0; s < KS; ++s) b[s] = *(const global_t<bf16x8>*)(wt + s * 512);
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
@@ -88,11 +101,11 @@ __device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ld
     for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         const int n = tile * 16 + r;
-        const global_t<uint16_t>* wrow = W + (size_t)n * Kp + kq;
+        const global_t<uint16_t>* wt = W + ((int64_t)tile * (Kp / 32) * 64 + lane) * 8;
         const uint16_t* arow = sA + r * ldA + kq;
         for (int k0 = 0; k0 < Kp; k0 += 32) {
             const bf16x8 a = *(const bf16x8*)(arow + k0);
-            const bf16x8 b = *(const global_t<bf16x8>*)(wrow + k0);
+            const bf16x8 b = *(const global_t<bf16x8>*)(wt + (k0 / 32) * 512);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }
 #pragma unroll

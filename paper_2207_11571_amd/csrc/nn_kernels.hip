@@ -66,7 +66,8 @@ __global__ void __launch_bounds__(kRowThreads) k_net_forcing(NetArgs na, int NP,
 
 // ------------------------------------------------------------------- weights
 
-// bf16 copies of W_l ([pout][pin]) and W_l^T ([pin][pout]), zero padded
+// bf16 copies of W_l ([pout][pin]) and W_l^T ([pin][pout]), zero padded, in
+// the fragment order of wfrag_index
 __global__ void __launch_bounds__(256) k_net_refresh(NetArgs na, const float* __restrict__ params,
                                                     uint16_t* __restrict__ wbf,
                                                     int64_t woff0, int l, int64_t wbf_off, int64_t wtbf_off) {
@@ -77,8 +78,8 @@ __global__ void __launch_bounds__(256) k_net_refresh(NetArgs na, const float* __
         const int o = idx / pin, i = idx - o * pin;
         const float w = (o < dout && i < din) ? params[woff0 + (int64_t)o * din + i] : 0.0f;
         const uint16_t h = f2bf(w);
-        wbf[wbf_off + (int64_t)o * pin + i] = h;
-        wbf[wtbf_off + (int64_t)i * pout + o] = h;
+        wbf[wbf_off + wfrag_index(o, i, pin)] = h;
+        wbf[wtbf_off + wfrag_index(i, o, pout)] = h;
     }
 }
 
@@ -273,7 +274,7 @@ __global__ void __launch_bounds__(kThreads) k_wgrad(GradArgs ga) {
 }
 
 // Adam update of parameter i (flat index) with gradient gi; weights also go
-// to their bf16 copies W_l [pout][pin] and W_l^T [pin][pout]
+// to their bf16 copies W_l [pout][pin] and W_l^T [pin][pout] (fragment order)
 __device__ __forceinline__ void adam_one(const AdamArgs& aa, const ParamMap& pm, int64_t i, float gi) {
     const float mi = aa.b1 * aa.m[i] + (1.0f - aa.b1) * gi;
     const float vi = aa.b2 * aa.v[i] + (1.0f - aa.b2) * gi * gi;
@@ -287,8 +288,8 @@ __device__ __forceinline__ void adam_one(const AdamArgs& aa, const ParamMap& pm,
         const int64_t w = i - pm.woff[l];
         const int o = (int)(w / pm.din[l]), ii = (int)(w - (int64_t)o * pm.din[l]);
         const uint16_t h = f2bf(pi);
-        aa.wbf[pm.wbo[l] + (int64_t)o * pm.pin[l] + ii] = h;
-        aa.wbf[pm.wtbo[l] + (int64_t)ii * pm.pout[l] + o] = h;
+        aa.wbf[pm.wbo[l] + wfrag_index(o, ii, pm.pin[l])] = h;
+        aa.wbf[pm.wtbo[l] + wfrag_index(ii, o, pm.pout[l])] = h;
     }
 }
 

@@ -52,13 +52,22 @@ def test_bf16_weight_copies_bitwise(B):
     model = B.Model(DIMS, B.pack_params(layers), NORM)
     torch.cuda.synchronize()
     wbf = model.wbf.cpu().numpy().view(np.uint16)
+
+    def unfragment(flat, rows, cols):
+        # the copies are in the matrix cores' fragment order: element [n][k]
+        # of a [rows][cols] matrix sits in the 1 KB block of (n // 16, k // 32)
+        # at lane n % 16 + 16 ((k % 32) // 8), entry k % 8
+        n, k = np.meshgrid(np.arange(rows), np.arange(cols), indexing="ij")
+        idx = (((n // 16) * (cols // 32) + k // 32) * 64 + n % 16 + 16 * ((k % 32) // 8)) * 8 + k % 8
+        return flat[idx]
+
     off = 0
     for W, _ in layers:
         out_d, in_d = W.shape
         pin, pout = (in_d + 31) // 32 * 32, (out_d + 31) // 32 * 32
-        Wb = wbf[off:off + pout * pin].reshape(pout, pin)
+        Wb = unfragment(wbf[off:off + pout * pin], pout, pin)
         off += pout * pin
-        WTb = wbf[off:off + pout * pin].reshape(pin, pout)
+        WTb = unfragment(wbf[off:off + pout * pin], pin, pout)
         off += pout * pin
         ref = (mlp.bf16_round(W).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
         assert np.array_equal(Wb[:out_d, :in_d], ref)
