@@ -113,6 +113,31 @@ __device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ld
     }
 }
 
+// Layers with K <= 32 * kMaxKS = 320 keep a wavefront's whole weight tile in
+// registers, so the next layer's tile can be loaded while the current one's
+// outputs are formed (below).
+constexpr int kMaxKS = 10;
+
+// issue the loads of this wavefront's fragments of column tile `tile` of W
+
+__device__ __forceinline__ void load_frags(bf16x8 (&b)[kMaxKS], const global_t<uint16_t>* W, int Kp, int tile, int lane) {
+    const int KS = Kp >> 5;
+    const global_t<uint16_t>* wt = W + ((int64_t)tile * KS * 64 + lane) * 8;
+#pragma unroll
+    for (int s = 0; s < kMaxKS; ++s)
+        if (s < KS) b[s] = *(const global_t<bf16x8>*)(wt + s * 512);
+}
+
+// C tile = A[16][Kp] (LDS rows from arow) times the fragments b
+__device__ __forceinline__ floatx4 mma_frags(const bf16x8 (&b)[kMaxKS], const uint16_t* arow, int Kp) {
+    const int KS = Kp >> 5;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < kMaxKS; ++s)
+        if (s < KS) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf16x8*)(arow + 32 * s), b[s], acc, 0, 0, 0);
+    return acc;
+}
+
 // normalised network input of node n of variable v, value qv (Sec. 2.2:
 // per-variable, or per-node when the model carries column statistics)
 __device__ __forceinline__ float net_input(const NetArgs& na, int NP, int v, int n, double qv) {
@@ -147,6 +172,59 @@ __device__ __forceinline__ void net_block_forward(const NetArgs& na, int NP, con
                                                   uint16_t* bufA, uint16_t* bufB, int ld, int wave, int lane) {
     const size_t vs = (size_t)T.E * NP;
     const int L = na.n_layers;
+    // Narrow layers: each wavefront's weight tile of the next layer is
+    // loaded as soon as the products of its last tile of this layer are
+    // issued, so the load latency overlaps the bias / activation epilogue
+    // and the block barrier instead of starting after them.
+    bool narrow = true;
+    for (int l = 0; l < L; ++l) narrow = narrow && na.pdims[l] <= 32 * kMaxKS;
+    if (narrow) {
+        const int r = lane & 15;
+        const int kq = 8 * (lane >> 4);
+        bf16x8 b[kMaxKS];
+        if (wave < na.pdims[1] / 16) load_frags(b, gmem(na.W[0]), na.pdims[0], wave, lane);
+        for (int l = 0; l < L; ++l) {
+            const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
+            const global_t<const float>* bias = gmem(na.b[l]);
+            const uint16_t* arow = bufA + r * ld + kq;
+            for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
+                if (tile != wave) load_frags(b, gmem(na.W[l]), Kp, tile, lane);
+                const floatx4 acc = mma_frags(b, arow, Kp);
+                if (tile + kRowWaves >= Np / 16 && l + 1 < L && wave < na.pdims[l + 2] / 16)
+                    load_frags(b, gmem(na.W[l + 1]), Np, wave, lane);
+                const int n = tile * 16 + r;
+                if (l < L - 1) {
+                    const float bn = n < Nd ? bias[n] : 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int m = 4 * (lane >> 4) + i;
+                        bufB[m * ld + n] = f2bf(n < Nd ? act_fwd(acc[i] + bn, na.act) : 0.0f);
+                    }
+                } else if (n < Nd) {
+                    const float bn = bias[n];
+                    const int j = n / NP, node = n - j * NP;
+                    const int vv = na.out_var[j];
+                    const int cc = vv * NP + node;
+                    const double sc = na.col ? na.mask[vv] * na.col[15 * NP + cc] : na.mask[vv] * na.sig_out[vv];
+                    const double sh = na.col ? na.mask[vv] * na.col[10 * NP + cc] : na.mask[vv] * na.mu_out[vv];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int e = e0 + 4 * (lane >> 4) + i;
+                        if (e < T.E) {
+                            const double s = sc * (double)(acc[i] + bn) + sh;
+                            global_t<double>* o = gmem(T.out) + vv * vs + (size_t)e * NP + node;
+                            *o = accumulate ? *o + s : s;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            uint16_t* tmp = bufA;
+            bufA = bufB;
+            bufB = tmp;
+        }
+        return;
+    }
     for (int l = 0; l < L; ++l) {
         const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
         const global_t<const float>* bias = gmem(na.b[l]);
