@@ -187,6 +187,9 @@ __device__ __forceinline__ void net_block_forward(const NetArgs& na, int NP, con
             const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
             const global_t<const float>* bias = gmem(na.b[l]);
             const uint16_t* arow = bufA + r * ld + kq;
+            // a wavefront with no tile in this layer but one in the next
+            if (l + 1 < L && wave >= Np / 16 && wave < na.pdims[l + 2] / 16)
+                load_frags(b, gmem(na.W[l + 1]), Np, wave, lane);
             for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
                 if (tile != wave) load_frags(b, gmem(na.W[l]), Kp, tile, lane);
                 const floatx4 acc = mma_frags(b, arow, Kp);

@@ -351,3 +351,50 @@ def test_forcing_and_gradients_P2(B):
         eW, eb = rel_l2(gW, rW), rel_l2(gb, rb)
         print("P2 layer", l, "grad rel L2", eW, eb)
         assert eW < 1e-2 and eb < 1e-2
+
+
+@pytest.mark.parametrize("dims", [[320, 96, 256, 160, 320], [320, 384, 320]])
+def test_forcing_and_gradients_other_widths(B, dims):
+    """Hidden widths other than 256 (P = 3, five variables in and out):
+    96 -> 256 -> 160 leaves wavefronts without a column tile in one layer
+    and with one in the next (forward and backward chains); 384 is wider
+    than the 320 columns a wavefront keeps in registers, so those layers run
+    the generic product.  Forcing on a perturbed 4^3 Taylor-Green state and
+    one training step's loss and gradients against the oracle."""
+    from oracle import dg, forcing, mlp
+    say("network widths", dims)
+    layers = synthetic.mlp_init(dims, seed=6)
+    layers = [(W, b + 0.01) for W, b in layers]
+    params, norm = _oracle_model(layers)
+    prm = dg.Params(N=4, P=3, Re=200.0)
+    q = dg.tgv_initial_condition(prm).copy()
+    q[1:4] += 0.05 * np.random.default_rng(10).standard_normal(q[1:4].shape)
+    qf = dg.to_flat(q)
+    ref = forcing.network_forcing(qf, params, norm)
+    m = B.Mesh(4, 3, 200.0)
+    model = B.Model(dims, B.pack_params(layers), NORM)
+    out = m.field(0.0)
+    B.nn_forcing(model, m, _to_gpu(qf), out)
+    torch.cuda.synchronize()
+    err = rel_l2(out.cpu().numpy(), ref)
+    print("forcing rel L2", err)
+    assert err < 1e-2
+    batch, n_p = 200, 64
+    rng = np.random.default_rng(11)
+    x = np.empty((batch, 320), dtype=np.float32)
+    x[:, :64] = 1.0 + 0.01 * rng.standard_normal((batch, 64))
+    x[:, 64:256] = rng.standard_normal((batch, 192))
+    x[:, 256:] = synthetic.TGV_ENERGY_LEVEL + rng.standard_normal((batch, 64))
+    y = (1e-3 * rng.standard_normal((batch, 320))).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    B.nn_train_step(model, _to_gpu(x, np.float32), _to_gpu(y, np.float32), lr=1e-3, loss=loss)
+    torch.cuda.synchronize()
+    xh = (x.astype(np.float64) - np.repeat(norm.mu_in, n_p)) / np.repeat(norm.sigma_in, n_p)
+    yt = (y.astype(np.float64) - np.repeat(norm.mu_out, n_p)) / np.repeat(norm.sigma_out, n_p)
+    loss_ref, grads = mlp.mse_loss_and_grads(params, xh, yt)
+    assert abs(loss.item() / loss_ref - 1) < 1e-2
+    g_gpu = B.unpack_params(model.grad.cpu().numpy().astype(np.float64), dims)
+    for l, ((gW, gb), (rW, rb)) in enumerate(zip(g_gpu, grads)):
+        eW, eb = rel_l2(gW, rW), rel_l2(gb, rb)
+        print("layer", l, "grad rel L2", eW, eb)
+        assert eW < 1e-2 and eb < 1e-2
