@@ -91,7 +91,8 @@ __global__ void __launch_bounds__(256) k_fill_f32(float* p, float v, size_t n) {
 
 // One row block: forward with LDS-resident activations, MSE loss in
 // normalised space, backward data chain dz_{l-1} = (dz_l W_l) * act'(h_l).
-// Writes transposed activations and output gradients for the weight products.
+// Writes transposed activations and output gradients for the weight products,
+// in fragment order over the batch (wfrag_index with K = Bp).
 __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArgs ta) {
     extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
     const int L = na.n_layers;
@@ -186,14 +187,14 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
         const int pd = na.pdims[l];
         for (int idx = t; idx < pd * kRows; idx += kRowThreads) {
             const int c = idx / kRows, r = idx - c * kRows;
-            gmem(ta.actT[l])[(size_t)c * Bp + r0 + r] = act(l)[r * ld + c];
+            gmem(ta.actT[l])[wfrag_index(c, r0 + r, Bp)] = act(l)[r * ld + c];
         }
     }
     {
         const int pd = na.pdims[L];
         for (int idx = t; idx < pd * kRows; idx += kRowThreads) {
             const int c = idx / kRows, r = idx - c * kRows;
-            gmem(ta.dzT[L - 1])[(size_t)c * Bp + r0 + r] = g0[r * ld + c];
+            gmem(ta.dzT[L - 1])[wfrag_index(c, r0 + r, Bp)] = g0[r * ld + c];
         }
     }
     // backward data chain
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
         __syncthreads();
         for (int idx = t; idx < Np * kRows; idx += kRowThreads) {
             const int c = idx / kRows, r = idx - c * kRows;
-            gmem(ta.dzT[l - 1])[(size_t)c * Bp + r0 + r] = gout[r * ld + c];
+            gmem(ta.dzT[l - 1])[wfrag_index(c, r0 + r, Bp)] = gout[r * ld + c];
         }
         for (int c = t; c < Np; c += kRowThreads) {
             float sacc = 0.0f;
@@ -243,21 +244,26 @@ __global__ void __launch_bounds__(kThreads) k_wgrad(GradArgs ga) {
     const int ks = blockIdx.y;
     const int kb = ks * ga.kchunk;
     const int ke = kb + ga.kchunk < Bp ? kb + ga.kchunk : Bp;
-    const int r = lane & 15, kq = 8 * (lane >> 4);
-    const uint16_t* arow0 = ga.dzT[l] + (size_t)(to * 32 + r) * Bp + kq;
-    const uint16_t* arow1 = arow0 + (size_t)16 * Bp;
-    const uint16_t* brow0 = ga.actT[l] + (size_t)(tii * 32 + r) * Bp + kq;
-    const uint16_t* brow1 = brow0 + (size_t)16 * Bp;
+    const int r = lane & 15;
+    // dzT and actT are in fragment order over the batch (wfrag_index with
+    // K = Bp): the 32-batch step s of 16-row tile t is the 1 KB block
+    // t * Bp / 32 + s, lane-major
+    const int ksteps = Bp / 32;
+    const global_t<uint16_t>* arow0 = gmem(ga.dzT[l]) + ((int64_t)(2 * to) * ksteps * 64 + lane) * 8;
+    const global_t<uint16_t>* arow1 = arow0 + (int64_t)ksteps * 512;
+    const global_t<uint16_t>* brow0 = gmem(ga.actT[l]) + ((int64_t)(2 * tii) * ksteps * 64 + lane) * 8;
+    const global_t<uint16_t>* brow1 = brow0 + (int64_t)ksteps * 512;
     floatx4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = kb; k0 < ke; k0 += 32) {
-        const bf16x8 a0 = *(const bf16x8*)(arow0 + k0);
-        const bf16x8 a1 = *(const bf16x8*)(arow1 + k0);
-        const bf16x8 b0 = *(const bf16x8*)(brow0 + k0);
-        const bf16x8 b1 = *(const bf16x8*)(brow1 + k0);
+        const int64_t o = (int64_t)(k0 / 32) * 512;
+        const bf16x8 a0 = *(const global_t<bf16x8>*)(arow0 + o);
+        const bf16x8 a1 = *(const global_t<bf16x8>*)(arow1 + o);
+        const bf16x8 b0 = *(const global_t<bf16x8>*)(brow0 + o);
+        const bf16x8 b1 = *(const global_t<bf16x8>*)(brow1 + o);
         acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
