@@ -152,9 +152,13 @@ static TrainLayout train_layout(const nn_model* m, int batch) {
     TrainLayout T;
     std::memset(&T, 0, sizeof(T));
     T.Bp = pad32(batch);
+    // the weight-gradient products split the batch into nks slices of at
+    // least 256 rows, at most eight (batch 4096: 0.0675 ms per Adam step
+    // against 0.071 with sixteen slices, whose partial sums double the
+    // traffic of the reduction; 0.0705 with four)
     T.nks = T.Bp / 256;
     if (T.nks < 1) T.nks = 1;
-    if (T.nks > 16) T.nks = 16;
+    if (T.nks > 8) T.nks = 8;
     T.nrb = T.Bp / 16;
     size_t off = 0;
     for (int l = 0; l < m->n_layers; ++l) {
