@@ -273,18 +273,21 @@ int rk_impl(const Mesh& m, double* q, double* k, double dt, int n_steps, const n
     DescList dl[4];
     for (int p = 0; p < 4; ++p) dl[p] = single_list(dd + p, m.E);
     DG_HIP(launch_traces(m.PP, dl[1], st));   // traces of q into qtr0
-    // forcing at every stage at P = 3: BR1 pass and network in one launch
-    const bool fused = model && !post && grad_net_fusable(model, m);
+    // P = 3 on a mesh that fills the GPU with 16-element blocks: the BR1
+    // pass and the network in one launch, at every stage (Eq. (4)) or, for
+    // the post-step correction (Algorithm 1), at the first stage, whose BR1
+    // pass reads the same state q^n the network is evaluated on
+    const bool fused = model && grad_net_fusable(model, m);
     int par = 0;
     for (int n = 0; n < n_steps; ++n) {
         // post-step correction (Algorithm 1): s from the state at the start of the step
-        if (model && post) {
+        if (model && post && !fused) {
             int rc = net_forcing_impl(model, m, q, (double*)(ws + L.forcing), /*accumulate=*/0, st);
             if (rc != DG_OK) return rc;
         }
         for (int s = 0; s < 3; ++s) {
             const DescList& l = dl[(post && model && s == 2 ? 2 : 0) + par];
-            if (fused) {
+            if (fused && (!post || s == 0)) {
                 int rc = grad_net_impl(model, m, l, q, (double*)(ws + L.forcing), st);
                 if (rc != DG_OK) return rc;
             } else {

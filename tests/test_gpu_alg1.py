@@ -122,15 +122,18 @@ def test_post_corrected_steps_match_oracle(B):
     assert torch.equal(qa, qb)
 
 
-def test_post_correction_is_dt_times_forcing_of_the_step_start(B):
+@pytest.mark.parametrize("N", [3, 16])
+def test_post_correction_is_dt_times_forcing_of_the_step_start(B, N):
     """One post-corrected step minus one plain step is dt s(q^n), s from
-    nn_forcing on the starting state (GPU against GPU: one rounding)."""
+    nn_forcing on the starting state (GPU against GPU: one rounding).  At
+    16^3 the network runs fused with the first stage's BR1 pass."""
     from oracle import dg
-    say("post correction = dt s(q^n)")
-    N, P, Re = 3, 3, 400.0
+    say("post correction = dt s(q^n)", N)
+    P, Re = 3, 400.0
     layers = synthetic.mlp_init(DIMS, seed=2)
     prm, q0 = _state(N, P, Re, seed=5)
     m = B.Mesh(N, P, Re)
+    m.ws.fill_(0x7F)     # garbage in the forcing buffer: the network's write must clear it
     model = B.Model(DIMS, B.pack_params(layers), NORM, activation="relu", train=False, in_vars=MOM, out_vars=MOM)
     dt = 1e-3
     qa, qb = _to_gpu(dg.to_flat(q0)), _to_gpu(dg.to_flat(q0))
