@@ -89,6 +89,23 @@ __global__ void __launch_bounds__(256) k_fill_f32(float* p, float v, size_t n) {
 
 // ------------------------------------------------------------------- training
 
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// Columns c < pd of the block's 16 LDS rows (rows r0 .. r0 + 15 of the
+// batch) to dst in fragment order over the batch (wfrag_index with K = Bp):
+// eight consecutive rows of a column are sixteen contiguous bytes there, so
+// each thread packs eight LDS values into one store.
+__device__ __forceinline__ void store_transposed(const uint16_t* src, int ld, int pd, global_t<uint16_t>* dst, int r0,
+                                                 int Bp, int t) {
+    for (int idx = t; idx < pd * 2; idx += kRowThreads) {
+        const int c = idx >> 1, g = 8 * (idx & 1);
+        u16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = src[(g + j) * ld + c];
+        *(global_t<u16x8>*)(dst + wfrag_index(c, r0 + g, Bp)) = v;
+    }
+}
+
 // One row block: forward with LDS-resident activations, MSE loss in
 // normalised space, backward data chain dz_{l-1} = (dz_l W_l) * act'(h_l).
 // Writes transposed activations and output gradients for the weight products,
@@ -183,20 +200,8 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
         gmem(ta.bias_part[L - 1])[(size_t)blockIdx.x * na.pdims[L] + c] = sacc;
     }
     // transposed activations and dz_{L-1}
-    for (int l = 0; l < L; ++l) {
-        const int pd = na.pdims[l];
-        for (int idx = t; idx < pd * kRows; idx += kRowThreads) {
-            const int c = idx / kRows, r = idx - c * kRows;
-            gmem(ta.actT[l])[wfrag_index(c, r0 + r, Bp)] = act(l)[r * ld + c];
-        }
-    }
-    {
-        const int pd = na.pdims[L];
-        for (int idx = t; idx < pd * kRows; idx += kRowThreads) {
-            const int c = idx / kRows, r = idx - c * kRows;
-            gmem(ta.dzT[L - 1])[wfrag_index(c, r0 + r, Bp)] = g0[r * ld + c];
-        }
-    }
+    for (int l = 0; l < L; ++l) store_transposed(act(l), ld, na.pdims[l], gmem(ta.actT[l]), r0, Bp, t);
+    store_transposed(g0, ld, na.pdims[L], gmem(ta.dzT[L - 1]), r0, Bp, t);
     // backward data chain
     uint16_t* gin = g0;
     uint16_t* gout = g1;
@@ -209,10 +214,7 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
             gout[m * ld + n] = f2bf(r0 + m < B ? d : 0.0f);
         });
         __syncthreads();
-        for (int idx = t; idx < Np * kRows; idx += kRowThreads) {
-            const int c = idx / kRows, r = idx - c * kRows;
-            gmem(ta.dzT[l - 1])[wfrag_index(c, r0 + r, Bp)] = gout[r * ld + c];
-        }
+        store_transposed(gout, ld, Np, gmem(ta.dzT[l - 1]), r0, Bp, t);
         for (int c = t; c < Np; c += kRowThreads) {
             float sacc = 0.0f;
             for (int rr = 0; rr < kRows; ++rr) sacc += bf2f(gout[rr * ld + c]);
