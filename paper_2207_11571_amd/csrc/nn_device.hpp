@@ -27,6 +27,22 @@ constexpr int kRowWaves = 16;     // row-block kernels: sixteen wavefronts share
 constexpr int kRowThreads = 64 * kRowWaves;
 constexpr int kLdPad = 8;      // LDS row padding (bf16 elements)
 
+// Weight fragments are read with buffer loads through a resource over one
+// layer's bf16 weights [Np][Kp]: one vector offset per lane, the 1 KB steps
+// of a tile as scalar offsets.  Plain global loads need an address register
+// of their own for every step past the 4 KB immediate offset.
+constexpr int kBufferWord3 = 0x00020000;   // fourth resource word, gfx9 family (32-bit data format)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t weight_rsrc(const __attribute__((address_space(1))) uint16_t* W,
+                                                               int Kp, int Np) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(const uint16_t*)W, 0, Np * Kp * 2, kBufferWord3);
+}
+
+// fragment step s of the tile whose lane offset (bytes) is vo
+__device__ __forceinline__ bf16x8 weight_frag(__amdgpu_buffer_rsrc_t rs, int vo, int s) {
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, s * 1024, 0));
+}
+
 // float32 -> bfloat16, round to nearest even (NaN kept quiet)
 __device__ __forceinline__ uint16_t f2bf(float x) {
     uint32_t u = __float_as_uint(x);
@@ -67,11 +83,12 @@ __device__ __forceinline__ void tile_mma_fixed(const uint16_t* __restrict__ sA, 
     const int kq = 8 * (lane >> 4);
     const int r = lane & 15;
     const uint16_t* arow = sA + r * ldA + kq;
+    const __amdgpu_buffer_rsrc_t rs = weight_rsrc(W, KP, Np);
     for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
-        const global_t<uint16_t>* wt = W + ((int64_t)tile * KS * 64 + lane) * 8;
+        const int vo = (tile * KS * 64 + lane) * 16;
         bf16x8 b[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) b[s] = *(const global_t<bf16x8>*)(wt + s * 512);
+        for (int s = 0; s < KS; ++s) b[s] = weight_frag(rs, vo, s);
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
@@ -119,13 +136,18 @@ __device__ __forceinline__ void tile_mma(const uint16_t* __restrict__ sA, int ld
 constexpr int kMaxKS = 10;
 
 // issue the loads of this wavefront's fragments of column tile `tile` of W
-
-__device__ __forceinline__ void load_frags(bf16x8 (&b)[kMaxKS], const global_t<uint16_t>* W, int Kp, int tile, int lane) {
+// [Np][Kp].  (Each load sits under its own branch, the count being known at
+// run time; with global loads and their per-step address registers the
+// compiler waited for all loads in flight before each step past the first
+// four, which the buffer loads avoid.)
+__device__ __forceinline__ void load_frags(bf16x8 (&b)[kMaxKS], const global_t<uint16_t>* W, int Kp, int Np, int tile,
+                                           int lane) {
     const int KS = Kp >> 5;
-    const global_t<uint16_t>* wt = W + ((int64_t)tile * KS * 64 + lane) * 8;
+    const __amdgpu_buffer_rsrc_t rs = weight_rsrc(W, Kp, Np);
+    const int vo = (tile * KS * 64 + lane) * 16;
 #pragma unroll
     for (int s = 0; s < kMaxKS; ++s)
-        if (s < KS) b[s] = *(const global_t<bf16x8>*)(wt + s * 512);
+        if (s < KS) b[s] = weight_frag(rs, vo, s);
 }
 
 // C tile = A[16][Kp] (LDS rows from arow) times the fragments b
@@ -182,19 +204,19 @@ __device__ __forceinline__ void net_block_forward(const NetArgs& na, int NP, con
         const int r = lane & 15;
         const int kq = 8 * (lane >> 4);
         bf16x8 b[kMaxKS];
-        if (wave < na.pdims[1] / 16) load_frags(b, gmem(na.W[0]), na.pdims[0], wave, lane);
+        if (wave < na.pdims[1] / 16) load_frags(b, gmem(na.W[0]), na.pdims[0], na.pdims[1], wave, lane);
         for (int l = 0; l < L; ++l) {
             const int Kp = na.pdims[l], Np = na.pdims[l + 1], Nd = na.dims[l + 1];
             const global_t<const float>* bias = gmem(na.b[l]);
             const uint16_t* arow = bufA + r * ld + kq;
             // a wavefront with no tile in this layer but one in the next
             if (l + 1 < L && wave >= Np / 16 && wave < na.pdims[l + 2] / 16)
-                load_frags(b, gmem(na.W[l + 1]), Np, wave, lane);
+                load_frags(b, gmem(na.W[l + 1]), Np, na.pdims[l + 2], wave, lane);
             for (int tile = wave; tile < Np / 16; tile += kRowWaves) {
-                if (tile != wave) load_frags(b, gmem(na.W[l]), Kp, tile, lane);
+                if (tile != wave) load_frags(b, gmem(na.W[l]), Kp, Np, tile, lane);
                 const floatx4 acc = mma_frags(b, arow, Kp);
                 if (tile + kRowWaves >= Np / 16 && l + 1 < L && wave < na.pdims[l + 2] / 16)
-                    load_frags(b, gmem(na.W[l + 1]), Np, wave, lane);
+                    load_frags(b, gmem(na.W[l + 1]), Np, na.pdims[l + 2], wave, lane);
                 const int n = tile * 16 + r;
                 if (l < L - 1) {
                     const float bn = n < Nd ? bias[n] : 0.0f;
