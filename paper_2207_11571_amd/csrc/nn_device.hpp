@@ -43,12 +43,13 @@ __device__ __forceinline__ bf16x8 weight_frag(__amdgpu_buffer_rsrc_t rs, int vo,
     return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, s * 1024, 0));
 }
 
-// float32 -> bfloat16, round to nearest even (NaN kept quiet)
+// float32 -> bfloat16, round to nearest even (NaN kept quiet); a select,
+// not a branch, for the NaN case
 __device__ __forceinline__ uint16_t f2bf(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x0040u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const uint32_t u = __float_as_uint(x);
+    const uint32_t r = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t qnan = (u >> 16) | 0x0040u;
+    return (uint16_t)((u & 0x7FFFFFFFu) > 0x7F800000u ? qnan : r);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
