@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
     auto act = [&](int l) { return smem + l * kRows * ld; };
     uint16_t* g0 = smem + L * kRows * ld;
     uint16_t* g1 = g0 + kRows * ld;
-    __shared__ float red[kRowThreads];
+    __shared__ float red[kRowWaves];
 
     const int r0 = blockIdx.x * kRows;
     const int t = threadIdx.x;
@@ -186,14 +186,18 @@ __global__ void __launch_bounds__(kRowThreads) k_train_rows(NetArgs na, TrainArg
             g0[m * ld + n] = f2bf(dy);
         });
     }
-    red[t] = lsum;
+    // the block's loss: a fixed butterfly within each wavefront, then
+    // wavefront 0 sums the sixteen partial sums in order (one barrier)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+    if (lane == 0) red[wave] = lsum;
     __syncthreads();
-    for (int w = kRowThreads / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
+    if (t == 0) {
+        float sum = 0.0f;
+        for (int w = 0; w < kRowWaves; ++w) sum += red[w];
+        ta.loss_part[blockIdx.x] = sum;
     }
-    if (t == 0) ta.loss_part[blockIdx.x] = red[0];
-    // row-block sums of dz for the bias gradients (g0 is complete after the barriers above)
+    // row-block sums of dz for the bias gradients (g0 is complete after the barrier above)
     for (int c = t; c < na.pdims[L]; c += kRowThreads) {
         float sacc = 0.0f;
         for (int rr = 0; rr < kRows; ++rr) sacc += bf2f(g0[rr * ld + c]);
