@@ -1014,13 +1014,30 @@ __device__ __forceinline__ void resid_element(const SolveDesc& D, int e, int t, 
     }
 
     if (t < NP) {
+        // every load of the update (the Runge-Kutta register, the post-step
+        // correction) issued before the first store, and the descriptor's
+        // fields read once: after a store the compiler reloads them, and a
+        // load after each store would cost a round trip per variable
+        const double dt = D.dt;
+        gdouble* kg = gmem(D.k);
+        gdouble* qg = gmem(D.q);
+        const double* postp = D.post;
+        double kold[5], pst[5];
+        if (!first_stage) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) kold[v] = QEARLY ? kp[v] : kg[v * vstride + node];
+        }
+        if (postp) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) pst[v] = gmem(postp)[v * vstride + node];
+        }
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            const double kk = first_stage ? D.dt * R[v] : rkA * (QEARLY ? kp[v] : gmem(D.k)[v * vstride + node]) + D.dt * R[v];
+            const double kk = first_stage ? dt * R[v] : rkA * kold[v] + dt * R[v];
             qn[v] += rkB * kk;
-            if (D.post) qn[v] += D.dt * gmem(D.post)[v * vstride + node];
-            gmem(D.k)[v * vstride + node] = kk;
-            gmem(D.q)[v * vstride + node] = qn[v];
+            if (postp) qn[v] += dt * pst[v];
+            kg[v * vstride + node] = kk;
+            qg[v * vstride + node] = qn[v];
         }
     }
     // the new state goes to an LDS area no thread reads any more: the first
