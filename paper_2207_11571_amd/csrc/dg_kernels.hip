@@ -1013,6 +1013,9 @@ __device__ __forceinline__ void resid_element(const SolveDesc& D, int e, int t, 
         return;
     }
 
+    // the trace buffer's address read before the update's stores (after
+    // them the compiler would read it from the descriptor again)
+    gdouble* const qtr_out = gmem(D.qtr_out);
     if (t < NP) {
         // every load of the update (the Runge-Kutta register, the post-step
         // correction) issued before the first store, and the descriptor's
@@ -1051,7 +1054,7 @@ __device__ __forceinline__ void resid_element(const SolveDesc& D, int e, int t, 
         for (int v = 0; v < 5; ++v) qs[v * NP + t] = qn[v];
     }
     __syncthreads();
-    write_traces<PP>(qs, B, t, e, gmem(D.qtr_out));
+    write_traces<PP>(qs, B, t, e, qtr_out);
 }
 
 // Residual (update == 0: out = p(q) + forcing) or Runge-Kutta stage
