@@ -230,6 +230,13 @@ DescList single_list(const SolveDesc* d, int E) {
     return dl;
 }
 
+DescList single_list(const SolveDesc* d, const SolveDesc& host, int E) {
+    DescList dl = single_list(d, E);
+    dl.inl = 1;
+    dl.d0 = host;
+    return dl;
+}
+
 // ----------------------------------------------------------------- internal API used by server/nn
 
 int residual_impl(const Mesh& m, const double* q, double* dqdt, char* ws, hipStream_t st) {
@@ -241,7 +248,7 @@ int residual_impl(const Mesh& m, const double* q, double* dqdt, char* ws, hipStr
     d.qtr_out = (double*)(ws + L.qtr0);
     SolveDesc* dd = (SolveDesc*)(ws + L.desc);
     DG_HIP(launch_write_descs(&d, 1, dd, st));
-    const DescList dl = single_list(dd, m.E);
+    const DescList dl = single_list(dd, d, m.E);
     DG_HIP(launch_traces(m.PP, dl, st));
     if (m.ph.viscous) DG_HIP(launch_grad(m.PP, dl, st));
     DG_HIP(launch_resid(m.PP, 0, dl, 0.0, 0.0, 1, st));
@@ -271,7 +278,7 @@ int rk_impl(const Mesh& m, double* q, double* k, double dt, int n_steps, const n
     SolveDesc* dd = (SolveDesc*)(ws + L.desc);
     DG_HIP(launch_write_descs(d, 4, dd, st));
     DescList dl[4];
-    for (int p = 0; p < 4; ++p) dl[p] = single_list(dd + p, m.E);
+    for (int p = 0; p < 4; ++p) dl[p] = single_list(dd + p, d[p], m.E);
     DG_HIP(launch_traces(m.PP, dl[1], st));   // traces of q into qtr0
     // P = 3 on a mesh that fills the GPU with 16-element blocks: the BR1
     // pass and the network in one launch, at every stage (Eq. (4)) or, for
@@ -478,7 +485,7 @@ int dg_profile_steps(const dg_mesh* mh, double* q, double* k, double dt, int32_t
     }
     SolveDesc* dd = (SolveDesc*)(ws + L.desc);
     DG_HIP(launch_write_descs(d, 2, dd, st));
-    const DescList dl[2] = {single_list(dd, m.E), single_list(dd + 1, m.E)};
+    const DescList dl[2] = {single_list(dd, d[0], m.E), single_list(dd + 1, d[1], m.E)};
     const int n_ev = 2 * (1 + 9 * n_steps);
     std::vector<hipEvent_t> ev(n_ev);
     for (auto& e : ev) DG_HIP(hipEventCreate(&e));

@@ -748,6 +748,20 @@ k_grad(DescList dl) {
     else grad_volume_form<PP>(dl);
 }
 
+// the same for one solve whose descriptor is in the kernel arguments
+template <int PP>
+__global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::GRAD_WPE)))
+k_grad1(DescList dl) {
+    if constexpr (PP >= 9) {
+        __shared__ double sh[GradFaceLds<PP>::N];
+        grad_face_element<PP>(dl.d0, blockIdx.x, threadIdx.x, c_basis[PP - 2], sh);
+    } else {
+        __shared__ double sh[GradLds<PP>::N];
+        double qn[5];
+        grad_volume_element<PP>(dl.d0, blockIdx.x, threadIdx.x, sh, qn);
+    }
+}
+
 // P = 3 with the forcing network at every stage (Eq. (4)): the BR1 pass of
 // sixteen elements, one per wavefront, and the network on the same sixteen
 // rows in one launch.  After the BR1 pass each wavefront holds its
@@ -1069,6 +1083,14 @@ k_resid(DescList dl, double rkA, double rkB, int first_stage) {
     resid_element<PP, UPDATE>(*dl.d[si], b - dl.blk[si], threadIdx.x, c_basis[PP - 2], sh, rkA, rkB, first_stage);
 }
 
+// the same for one solve whose descriptor is in the kernel arguments
+template <int PP, int UPDATE>
+__global__ void __launch_bounds__(Shape<PP>::NT) __attribute__((amdgpu_waves_per_eu(Shape<PP>::WPE)))
+k_resid1(DescList dl, double rkA, double rkB, int first_stage) {
+    __shared__ double sh[ResidLds<PP>::N];
+    resid_element<PP, UPDATE>(dl.d0, blockIdx.x, threadIdx.x, c_basis[PP - 2], sh, rkA, rkB, first_stage);
+}
+
 // The same for one solve whose blocks fill a CU each (P = 8): one block per
 // CU walks the elements b, b + G, b + 2G, ... (G blocks), which spares the
 // launch of a block per element and lets each block's next element start as
@@ -1371,6 +1393,10 @@ hipError_t launch_traces(int PPv, const DescList& dl, hipStream_t st) {
 
 hipError_t launch_grad(int PPv, const DescList& dl, hipStream_t st) {
     const int nb = dl.blk[dl.n];
+    if (dl.n == 1 && dl.inl) {
+        DG_DISPATCH_PP(PPv, hipLaunchKernelGGL(k_grad1<PP>, dim3(nb), dim3(Shape<PP>::NT), 0, st, dl));
+        return hipGetLastError();
+    }
     DG_DISPATCH_PP(PPv, hipLaunchKernelGGL(k_grad<PP>, dim3(nb), dim3(Shape<PP>::NT), 0, st, dl));
     return hipGetLastError();
 }
@@ -1427,6 +1453,16 @@ hipError_t launch_resid(int PPv, int update, const DescList& dl, double rkA, dou
             hipLaunchKernelGGL((k_resid_loop<9, 1>), dim3(grid), dim3(Shape<9>::NT), 0, st, dl, rkA, rkB, first_stage);
         else
             hipLaunchKernelGGL((k_resid_loop<9, 0>), dim3(grid), dim3(Shape<9>::NT), 0, st, dl, rkA, rkB, first_stage);
+        return hipGetLastError();
+    }
+    if (dl.n == 1 && dl.inl) {
+        if (update) {
+            DG_DISPATCH_PP(PPv, hipLaunchKernelGGL((k_resid1<PP, 1>), dim3(nb), dim3(Shape<PP>::NT), 0, st, dl, rkA,
+                                                   rkB, first_stage));
+        } else {
+            DG_DISPATCH_PP(PPv, hipLaunchKernelGGL((k_resid1<PP, 0>), dim3(nb), dim3(Shape<PP>::NT), 0, st, dl, rkA,
+                                                   rkB, first_stage));
+        }
         return hipGetLastError();
     }
     if (update) {

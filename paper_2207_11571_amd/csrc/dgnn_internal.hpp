@@ -73,6 +73,12 @@ struct DescList {
     const SolveDesc* d[kMaxDescs];
     int blk[kMaxDescs + 1];
     int n;
+    // one solve whose descriptor the host also has: a copy travels in the
+    // kernel arguments (inl = 1), so the stage kernels read its fields
+    // there instead of through the pointer (two dependent loads fewer
+    // before a block's first data load)
+    int inl;
+    SolveDesc d0;
 };
 
 // Forcing-network description passed by value to the network kernels.
@@ -232,6 +238,8 @@ extern const double kRkA[3];
 extern const double kRkB[3];
 int make_mesh(const dg_params* prm, Mesh& M);
 DescList single_list(const SolveDesc* d, int E);
+// the same with the host's copy of the descriptor carried along
+DescList single_list(const SolveDesc* d, const SolveDesc& host, int E);
 int residual_impl(const Mesh& m, const double* q, double* dqdt, char* ws, hipStream_t st);
 int diag_impl(const Mesh& m, const double* q, double* out_dev, char* ws, hipStream_t st);
 int project_impl(const Mesh& src, const Mesh& dst, const double* f_src, double* f_dst, hipStream_t st);
