@@ -332,7 +332,7 @@ def main():
                 "counter_frac": None if traffic is None else traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "stage_algorithmic_frac": case["dof_updates_per_s"] * ALG_BYTES_RESID / (HBM_PEAK_GBS * 1e9)}
 
-    roofline = resid_roofline(head, "k_resid<7,1,*> (residual + RK stage update, 16^3 P=6)", "k_resid_p6")
+    roofline = resid_roofline(head, "k_resid1<7,1> (residual + RK stage update, 16^3 P=6, one solve: descriptor in the kernel arguments)", "k_resid_p6")
     roofline["p8"] = resid_roofline(p8, "k_resid_loop<9,1> (residual + RK stage update, 16^3 P=8, one block per CU walking the elements)", "k_resid_p8")
     stage_alg_frac = roofline["stage_algorithmic_frac"]
 
