@@ -769,7 +769,8 @@ k_grad1(DescList dl) {
 // element's normalised network input row straight into LDS instead of the
 // network gathering the state from HBM again, and the layers follow in the
 // same block.  The same device code as k_grad and k_net_forcing, so the same
-// numbers.  One solve per launch, E a multiple of 16.
+// numbers.  One solve per launch (its descriptor in the kernel arguments),
+// E a multiple of 16.
 template <int PP>
 __global__ void __launch_bounds__(kRowThreads) k_grad_net(DescList dl, NetArgs na, NetTarget T) {
     using S = Shape<PP>;
@@ -782,7 +783,7 @@ __global__ void __launch_bounds__(kRowThreads) k_grad_net(DescList dl, NetArgs n
     const int ld = pmax + kLdPad;
     uint16_t* bufA = (uint16_t*)(gsm + kRowWaves * GradLds<PP>::N);
     uint16_t* bufB = bufA + kRows * ld;
-    const SolveDesc& D = *dl.d[0];
+    const SolveDesc& D = dl.d0;   // one solve, its descriptor in the arguments
     const int e0 = blockIdx.x * kRows;
 
     double qn[5];
@@ -1418,7 +1419,7 @@ int cu_count() {
 }
 
 hipError_t launch_grad_net(int PPv, const DescList& dl, const NetArgs& na, const NetTarget& T, hipStream_t st) {
-    if (PPv != 4 || dl.n != 1 || T.E % kRows != 0 || na.dims[0] != na.n_in * 64) return hipErrorInvalidValue;
+    if (PPv != 4 || dl.n != 1 || !dl.inl || T.E % kRows != 0 || na.dims[0] != na.n_in * 64) return hipErrorInvalidValue;
     int pmax = 0;
     for (int l = 0; l <= na.n_layers; ++l) pmax = pmax > na.pdims[l] ? pmax : na.pdims[l];
     const size_t smem = (size_t)kRowWaves * GradLds<4>::N * sizeof(double) +
