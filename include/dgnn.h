@@ -284,11 +284,11 @@ int nn_data_stats(const float* x, const float* y, int64_t rows, int32_t n_p, dou
  *
  * Fallback of the learned part: the uncorrected low-order evolution (Eq. (3),
  * the base method of Sec. 2.1) backs every corrected solve.  The server
- * judges a corrected solve's state after every round of steps and at each of
+ * checks a corrected solve's state after every round of steps and at each of
  * its kinetic-energy records: when a value is not finite, or the kinetic
  * energy exceeds (1 + 1e-3) times its initial value (the Taylor-Green flow
  * decays, so the forcing is driving it), the solve returns to the copy of
- * its state taken at the start of that round (already judged healthy),
+ * its state taken at the start of that round (already checked healthy),
  * drops the records after it and continues uncorrected to t_end.
  * solve_status reports fallback = 1 and the step it continued from; the
  * footprint of a corrected solve includes that state copy.  A non-finite

@@ -20,8 +20,8 @@
 //
 // Fallback of the learned part: a corrected solve (network forcing, Eq. (4),
 // or Algorithm 1's correction) keeps a copy of its state from the start of
-// each round, a state already judged healthy.  At the end of every round its
-// state is judged again (finite diagnostics, kinetic energy not above
+// each round, a state already checked healthy.  At the end of every round its
+// state is checked again (finite diagnostics, kinetic energy not above
 // (1 + kFallbackKeRise) times the initial value -- the Taylor-Green flow
 // decays, so a rise means the forcing is driving it); when that or any of
 // the round's kinetic-energy records fails, the solve returns to the copy,
@@ -385,20 +385,20 @@ static bool record_healthy(const Solve* s, const double* rec) {
 static bool collect(solve_server* S, Solve* s) {
     const size_t n = s->pending_t.size();
     double health[kDiagDoubles];
-    const bool judge = s->nn_active;
+    const bool check = s->nn_active;
     if (n > 0 && hipMemcpy(S->pinned, s->hist, n * kDiagDoubles * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
         std::lock_guard<std::mutex> lk(S->mu);
         s->error = DG_EHIP;
         return false;
     }
-    if (judge && hipMemcpy(health, s->health, sizeof(health), hipMemcpyDeviceToHost) != hipSuccess) {
+    if (check && hipMemcpy(health, s->health, sizeof(health), hipMemcpyDeviceToHost) != hipSuccess) {
         std::lock_guard<std::mutex> lk(S->mu);
         s->error = DG_EHIP;
         return false;
     }
     std::lock_guard<std::mutex> lk(S->mu);
-    bool bad = judge && !record_healthy(s, health);
-    for (size_t r = 0; r < n && judge && !bad; ++r) bad = !record_healthy(s, S->pinned + r * kDiagDoubles);
+    bool bad = check && !record_healthy(s, health);
+    for (size_t r = 0; r < n && check && !bad; ++r) bad = !record_healthy(s, S->pinned + r * kDiagDoubles);
     const double t_ckpt = s->ckpt_steps * s->dt;
     for (size_t r = 0; r < n; ++r) {
         const double* rec = S->pinned + r * kDiagDoubles;
@@ -487,7 +487,7 @@ static void server_loop(solve_server* S) {
             hipStream_t gst = S->gst[g.first];
             int64_t n_g = 0;
             for (Solve* s : g.second) n_g = std::max(n_g, plan.at(s));
-            // corrected solves: copy of the (already judged) state the round starts from
+            // corrected solves: copy of the (already checked) state the round starts from
             for (Solve* s : g.second)
                 if (s->nn_active && rc == DG_OK) {
                     s->ckpt_steps = s->steps;

@@ -256,7 +256,7 @@ def test_fallback_after_blow_up(B):
     assert len(ke) == st.n_steps + 1 and np.all(np.diff(ke[:, 0]) > 0)
 
 
-def test_fallback_continues_from_the_last_judged_state(B):
+def test_fallback_continues_from_the_last_checked_state(B):
     """A constant forcing of the x-momentum (0.2 per unit time, from a
     network whose only non-zero parameters are output biases) adds kinetic
     energy faster than the Re-200 flow dissipates it: the oracle puts the
