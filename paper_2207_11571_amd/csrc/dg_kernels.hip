@@ -471,12 +471,29 @@ struct GradLds {
     static constexpr int N = cmax(12 * Shape<PP>::NP, 5 * Shape<PP>::NP + 24 * Shape<PP>::NF);
 };
 
+// The barrier between two phases of one element's work: the block's, or,
+// where one wavefront owns the element and its LDS area, that wavefront's
+// (its LDS operations complete in order, so the fences only keep the
+// compiler from moving LDS accesses across it).
+template <bool WAVE>
+__device__ __forceinline__ void element_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // element e of solve D, thread t of the element's Shape<PP>::NT, LDS area sh
-// of GradLds<PP>::N doubles; the node's state is left in qn (t < NP)
-template <int PP>
+// of GradLds<PP>::N doubles; the node's state is left in qn (t < NP).  WAVE:
+// the element is one wavefront's alone (Shape<PP>::NT == 64)
+template <int PP, bool WAVE = false>
 __device__ __forceinline__ void grad_volume_element(const SolveDesc& D, int e, int t, double* __restrict__ sh,
                                                     double qn[5]) {
     using S = Shape<PP>;
+    static_assert(!WAVE || S::NT == 64, "a wavefront per element");
     constexpr int NP = S::NP, NF = S::NF;
     double* what = sh + 5 * NP;                  // [6][4][NF] common BR1 values
     const Phys ph = D.ph;
@@ -523,21 +540,21 @@ __device__ __forceinline__ void grad_volume_element(const SolveDesc& D, int e, i
 #pragma unroll
         for (int c = 0; c < 4; ++c) sh[c * NP + t] = w[c];
     }
-    __syncthreads();
+    element_sync<WAVE>();
     double g[3][4];
     if (t < NP) {
         weak_deriv<PP, 0, 4>(sh, what, B, t, ph.s, g[0]);
         weak_deriv<PP, 1, 4>(sh, what, B, t, ph.s, g[1]);
         weak_deriv<PP, 2, 4>(sh, what, B, t, ph.s, g[2]);
     }
-    __syncthreads();
+    element_sync<WAVE>();
     if (t < NP) {
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
             for (int c = 0; c < 4; ++c) sh[(d * 4 + c) * NP + t] = g[d][c];
     }
-    __syncthreads();
+    element_sync<WAVE>();
 #pragma unroll
     for (int r = 0; r < S::TPT; ++r) {
         const int tau = t + r * S::NT;
@@ -764,7 +781,9 @@ k_grad1(DescList dl) {
 
 // P = 3 with the forcing network at every stage (Eq. (4)): the BR1 pass of
 // sixteen elements, one per wavefront, and the network on the same sixteen
-// rows in one launch.  After the BR1 pass each wavefront holds its
+// rows in one launch.  Each wavefront works on its own element in its own
+// LDS area, so between the BR1 pass's phases it waits for itself only, not
+// for the block.  After the BR1 pass each wavefront holds its
 // element's state in registers (node n in lane n), so it writes the
 // element's normalised network input row straight into LDS instead of the
 // network gathering the state from HBM again, and the layers follow in the
@@ -787,7 +806,7 @@ __global__ void __launch_bounds__(kRowThreads) k_grad_net(DescList dl, NetArgs n
     const int e0 = blockIdx.x * kRows;
 
     double qn[5];
-    grad_volume_element<PP>(D, e0 + wave, lane, gsm + wave * GradLds<PP>::N, qn);
+    grad_volume_element<PP, true>(D, e0 + wave, lane, gsm + wave * GradLds<PP>::N, qn);
 
     // row `wave` of the network input: column j NP + n is node n of
     // variable in_var[j]
